@@ -1,0 +1,233 @@
+/*
+ * pcr.h -- C ABI of the MI355X (gfx950) library for volumetric image
+ * reconstruction and tumour localisation from a single cone-beam x-ray
+ * projection under a PCA lung-motion model (Li et al., "Real-time volumetric
+ * image reconstruction and 3D tumor localization based on a single x-ray
+ * projection image for lung cancer radiotherapy").
+ *
+ * Method (section 2): the deformation x = mean + U w (eq. (1), eq. (2)
+ * constraint) warps the reference image f0 by trilinear interpolation
+ * (pull-back, f(p) = f0(p + x(p))); the cost J = |P f - a y - b|^2 (eq. (2))
+ * is minimised by alternating gradient descent on w with an Armijo line
+ * search (eq. (3)) and the closed-form fit of (a, b) (eq. (4)); the gradient
+ * is 2 U^T (df/dx)^T P^T (P f - a y - b); the tumour position is the inverse
+ * (push-forward) deformation of its reference position (section 2.3).
+ *
+ * Conventions shared by every entry point:
+ *   - All functions are extern "C", never throw, and return a pcr_status.
+ *     On failure a description is available from pcr_last_error() (a
+ *     thread-local string valid until the next call on the same thread).
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller
+ *     (e.g. torch tensors); *_host pointers and plain double* scalars are
+ *     host memory.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; the call returns without synchronising unless
+ *     it has to return host values (cost, gradient, solver results,
+ *     tumour position), in which case it synchronises that stream only.
+ *   - Volumes are [nz][ny][nx] (x fastest, flat index i + nx*(j + ny*k)),
+ *     the grid origin is the centre of voxel (0,0,0) in mm.
+ *   - DVFs are pull-back displacements in mm, structure of arrays [3][N]
+ *     (x, y, z components, N = nx*ny*nz).  Eigenvector fields are
+ *     [K][3][N].  Projections are [nv][nu] (u fastest).
+ *   - Cone-beam geometry: rotation about z through the isocentre; source
+ *     iso + (SAD sin t, -SAD cos t, 0), detector centre
+ *     iso + (-(SDD-SAD) sin t, (SDD-SAD) cos t, 0), detector axes
+ *     e_u = (cos t, sin t, 0), e_v = (0, 0, 1); pixel (iu, iv) centre
+ *     c + ((iu-(nu-1)/2) du + off_u) e_u + ((iv-(nv-1)/2) dv + off_v) e_v.
+ *   - The projection P samples every ray at t = n*step_mm from the source
+ *     (all integers n whose sample lies between source and pixel) with
+ *     trilinear interpolation, the image being zero outside its grid, and
+ *     returns step_mm * (sum of the samples).  P^T is its exact transpose.
+ *   - Compute precision is PCR_F32 or PCR_F64; the reference image and the
+ *     motion model may additionally be stored as PCR_BF16 or PCR_F16 (read
+ *     and widened to the compute type).  Detector-wide and volume-wide
+ *     reductions (cost, regression sums, gradient) accumulate in FP64.
+ *   - Inputs are validated before any launch: null pointers, non-positive
+ *     sizes or spacings, impossible geometry and non-finite host scalars
+ *     return PCR_EINVAL and enqueue nothing.
+ */
+#ifndef PCR_H
+#define PCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pcr_status;
+#define PCR_OK 0
+#define PCR_EINVAL (-1)    /* bad shape, dtype, geometry, option or null pointer */
+#define PCR_ENOMEM (-2)    /* device or host allocation failed */
+#define PCR_EDEVICE (-3)   /* HIP runtime error (details in pcr_last_error) */
+#define PCR_ENOCONV (-4)   /* line search exhausted or iteration cap hit before the
+                              gradient tolerance; outputs hold the last accepted iterate */
+#define PCR_EDIVERGE (-5)  /* fixed point did not converge; last iterate returned */
+#define PCR_EBUSY (-6)     /* serving admission refused (memory budget or slots) */
+
+typedef enum pcr_dtype { PCR_F32 = 0, PCR_F64 = 1, PCR_BF16 = 2, PCR_F16 = 3 } pcr_dtype;
+
+typedef struct pcr_grid {
+    int32_t n[3];          /* nx, ny, nz (> 0) */
+    double spacing_mm[3];  /* voxel size (> 0) */
+    double origin_mm[3];   /* centre of voxel (0,0,0) */
+} pcr_grid;
+
+typedef struct pcr_geom {
+    double angle_rad;      /* gantry angle t */
+    double sad_mm;         /* source-isocentre distance (> 0) */
+    double sdd_mm;         /* source-detector distance (> sad_mm) */
+    int32_t nu, nv;        /* detector columns and rows (> 0) */
+    double du_mm, dv_mm;   /* pixel pitch at the detector plane (> 0) */
+    double off_u_mm, off_v_mm; /* detector offsets along e_u, e_v */
+    double step_mm;        /* ray sample spacing (> 0) */
+    double iso_mm[3];      /* isocentre position */
+} pcr_geom;
+
+/* PCA motion model, eq. (1): x = mean + sum_k scale_k w_k U_k.  `mean` is
+ * [3][N] and `U` is [K][3][N], both device pointers of dtype `storage`
+ * (F32, F64, BF16 or F16).  `scale` is a host array [K] (NULL = all 1): a
+ * field stored divided by scale_k (FP16 storage keeps |U_k| <= 1 so that
+ * small entries stay out of the subnormal range). */
+typedef struct pcr_model {
+    int32_t K;             /* 1..8 */
+    pcr_dtype storage;
+    const void* mean;
+    const void* U;
+    const double* scale;
+} pcr_model;
+
+/* Gradient evaluation in the solver and in pcr_cost_grad. */
+#define PCR_GRAD_FUSED 0   /* d J/d w_k = 2 <r, P h_k> with h_k = (df/dx) . u_k: one
+                              (K+1)-channel ray march returns J and the gradient at
+                              any (a, b) -- the same number as the adjoint form */
+#define PCR_GRAD_ADJOINT 1 /* the paper's order: g = P^T (2r) by scatter, then
+                              sum_v g[v] (df/dx)[v] . u_k[v] */
+
+/* Options of the alternating algorithm (section 2.2).  The paper fixes the
+ * structure (Armijo's rule on w with a, b fixed; closed-form a, b; stop on a
+ * small gradient or an iteration cap); the constants are this library's:
+ * defaults from pcr_solve_opts_default(). */
+typedef struct pcr_solve_opts {
+    int32_t max_iter;        /* iteration cap (default 50) */
+    int32_t max_backtracks;  /* Armijo trials per iteration (default 30) */
+    double sigma;            /* sufficient decrease: accept J' <= J - sigma mu |g|^2 (1e-4) */
+    double beta;             /* step shrink per rejected trial (0.5) */
+    double eps_g;            /* stop when |g_n| <= eps_g |g_0| (1e-4) */
+    double step0;            /* first trial of a solve moves w by this distance (> 0);
+                                later iterations start from the last accepted step / beta */
+    double fixed_mu;         /* > 0: constant step mu, no line search (default 0) */
+    int32_t grad_mode;       /* PCR_GRAD_FUSED (default) or PCR_GRAD_ADJOINT */
+    int32_t localize;        /* nonzero: localise the tumour after the solve */
+    double p_ref_mm[3];      /* tumour position in the reference image */
+    double fp_tol_mm;        /* fixed-point stop: update shorter than this (1e-6) */
+    int32_t fp_max_iter;     /* fixed-point iteration cap (200) */
+} pcr_solve_opts;
+
+typedef struct pcr_solve_stats {
+    int32_t status;          /* same as the return value */
+    int32_t iterations;      /* accepted gradient steps */
+    int32_t trials;          /* line-search trials (projections of a trial w) */
+    int32_t fp_iterations;   /* fixed-point iterations of the localisation */
+    int32_t fp_status;       /* PCR_OK or PCR_EDIVERGE */
+    double J0, J;            /* cost after the first step 2, and at the result */
+    double gnorm0, gnorm;    /* |dJ/dw| at the start and at the result */
+    double a, b;             /* intensity fit at the result */
+    double tumor_mm[3];      /* localised tumour position (if requested) */
+} pcr_solve_stats;
+
+typedef struct pcr_ctx pcr_ctx;
+
+/* ------------------------------------------------------------------------ */
+const char* pcr_version(void);
+const char* pcr_last_error(void);
+void pcr_solve_opts_default(pcr_solve_opts* opts);
+
+/* DVF composition (eq. (2) constraint, eq. (1)): dvf = mean + U (scale * w).
+ * w_host[K] host doubles; dvf_dev [3][N] of dtype `compute` (F32 or F64),
+ * overwritten. */
+pcr_status pcr_dvf_compose(const pcr_grid* grid, const pcr_model* model,
+                           const double* w_host, pcr_dtype compute, void* dvf_dev,
+                           void* stream);
+
+/* Pull-back warp (sections 2.2-2.3): f[v] = T[f0](v + dvf[v] / spacing),
+ * trilinear, f0 = 0 outside its grid.  f0_dev [N] of dtype f0_dtype (any);
+ * dvf_dev [3][N] and f_dev [N] of dtype `compute` (F32 or F64); f_dev is
+ * overwritten and must not alias f0_dev. */
+pcr_status pcr_warp_volume(const pcr_grid* grid, pcr_dtype f0_dtype, const void* f0_dev,
+                           pcr_dtype compute, const void* dvf_dev, void* f_dev,
+                           void* stream);
+
+/* Transpose of the warp as a linear map of the reference image (the
+ * gradient with respect to f0): out = W^T g.  dvf_dev [3][N], g_dev [N],
+ * out_dev [N], all of dtype `compute`; out_dev is overwritten.  Uses
+ * floating-point atomics: the summation order, hence the last bits, may
+ * vary between runs. */
+pcr_status pcr_warp_adjoint(const pcr_grid* grid, pcr_dtype compute, const void* dvf_dev,
+                            const void* g_dev, void* out_dev, void* stream);
+
+/* Forward projection P vol (eq. (2)'s projection matrix, discretised as in
+ * the conventions above).  vol_dev [N] and proj_dev [nv][nu] of dtype
+ * `compute` (F32 or F64); proj_dev is overwritten.  Allocates a padded
+ * device copy of the volume per call (library-owned scratch, reused). */
+pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom,
+                               pcr_dtype compute, const void* vol_dev, void* proj_dev,
+                               void* stream);
+
+/* Backprojection P^T resid, the exact transpose of pcr_forward_project (the
+ * P^T of the gradient formula in section 2.2; no factor 2).  resid_dev
+ * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  Uses
+ * floating-point atomics (order-dependent last bits). */
+pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom,
+                                    pcr_dtype compute, const void* resid_dev,
+                                    void* vol_dev, void* stream);
+
+/* Solver context: binds a grid, a motion model and a reference image (all
+ * caller-owned device memory that must outlive the context) and owns the
+ * device scratch of the solve (a zero-padded multi-channel copy of the warped
+ * image, reduction partials, pinned host staging).  compute = F32 or F64.
+ * One context per host thread; calls on one context must not overlap. */
+pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtype f0_dtype,
+                          const void* f0_dev, pcr_dtype compute, pcr_ctx** out);
+void pcr_ctx_destroy(pcr_ctx* ctx);
+/* Bytes of device memory the context holds. */
+size_t pcr_ctx_device_bytes(const pcr_ctx* ctx);
+
+/* Cost J(w, a, b) (eq. (2)) and its gradient dJ/dw (section 2.2, with the
+ * factor 2) for the measured projection y_dev [nv][nu] (dtype = the
+ * context's compute dtype) at geometry `geom`.  grad_host[K].  grad_mode is
+ * PCR_GRAD_FUSED or PCR_GRAD_ADJOINT.  Synchronises `stream`. */
+pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
+                         const double* w_host, double a, double b, int32_t grad_mode,
+                         double* cost_host, double* grad_host, void* stream);
+
+/* One per-projection solve (section 2.2): (a, b) from step 2 at the warm
+ * start w_inout, then alternate Armijo gradient steps on w and step 2 until
+ * |g| <= eps_g |g_0|, max_iter, or line-search exhaustion; optionally
+ * localise the tumour (section 2.3).  w_inout[K] is the warm start on entry
+ * (section 4: the previous frame's w) and the result on exit; ab_out[2]
+ * (may be NULL); stats may be NULL.  Returns PCR_OK or PCR_ENOCONV (result
+ * still valid) or an error.  Synchronises `stream` once per line-search
+ * trial. */
+pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev,
+                                           const pcr_geom* geom, const pcr_solve_opts* opts,
+                                           double* w_inout, double* ab_out,
+                                           pcr_solve_stats* stats, void* stream);
+
+/* Tumour localisation (section 2.3): the point p with p + x(p) = p_ref for
+ * the pull-back DVF x = mean + U (scale * w), by the fixed-point iteration
+ * p <- p_ref - x(p) (Chen et al., the paper's ref. 13) evaluated at that
+ * point only, in FP64 on the device, x interpolated trilinearly with
+ * clamp-to-edge.  Stops when the update is shorter than tol_mm or after
+ * max_iter iterations (then PCR_EDIVERGE with the last iterate).  iters may
+ * be NULL.  Synchronises `stream`. */
+pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model,
+                              const double* w_host, const double p_ref_mm[3], double tol_mm,
+                              int32_t max_iter, double p_out_mm[3], int32_t* iters,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCR_H */

@@ -1,0 +1,706 @@
+// C ABI of the reconstruction library: validation, device scratch, the
+// solver context and the per-projection solve (section 2.2 of Li et al.).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcr.h"
+#include "pcr_internal.h"
+
+using namespace pcr;
+
+#define PCR_VERSION_STRING "pcr 0.1.0 (gfx950)"
+
+// ------------------------------------------------------------- errors ----
+static thread_local std::string g_err;
+
+static pcr_status fail(pcr_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? PCR_ENOMEM : PCR_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+#define PCR_TRY(expr)                                                                        \
+    do {                                                                                     \
+        pcr_status s_ = (expr);                                                              \
+        if (s_ != PCR_OK) return s_;                                                         \
+    } while (0)
+
+// --------------------------------------------------------- validation ----
+static size_t dtype_size(pcr_dtype d)
+{
+    switch (d) {
+    case PCR_F32: return 4;
+    case PCR_F64: return 8;
+    case PCR_BF16: return 2;
+    case PCR_F16: return 2;
+    }
+    return 0;
+}
+
+static pcr_status check_grid(const pcr_grid* g)
+{
+    if (!g) return fail(PCR_EINVAL, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] <= 0) return fail(PCR_EINVAL, "grid n[%d] = %d must be > 0", a, g->n[a]);
+        if (!(g->spacing_mm[a] > 0) || !std::isfinite(g->spacing_mm[a]))
+            return fail(PCR_EINVAL, "grid spacing[%d] must be finite and > 0", a);
+        if (!std::isfinite(g->origin_mm[a])) return fail(PCR_EINVAL, "grid origin must be finite");
+    }
+    if (g->n[2] > 65535 || (g->n[1] + 3) / 4 > 65535)
+        return fail(PCR_EINVAL, "grid n = (%d, %d, %d) exceeds the launch limits", g->n[0], g->n[1], g->n[2]);
+    double cells = (double)(g->n[0] + 3) * (g->n[1] + 3) * (g->n[2] + 3);
+    if (cells > 2.0e9) return fail(PCR_EINVAL, "grid too large (%.3g padded cells)", cells);
+    return PCR_OK;
+}
+
+static pcr_status check_geom(const pcr_geom* G)
+{
+    if (!G) return fail(PCR_EINVAL, "geometry is NULL");
+    const double v[] = {G->angle_rad, G->sad_mm, G->sdd_mm, G->du_mm, G->dv_mm, G->off_u_mm,
+                        G->off_v_mm, G->step_mm, G->iso_mm[0], G->iso_mm[1], G->iso_mm[2]};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(PCR_EINVAL, "geometry has a non-finite value");
+    if (!(G->sad_mm > 0)) return fail(PCR_EINVAL, "sad_mm must be > 0");
+    if (!(G->sdd_mm > G->sad_mm)) return fail(PCR_EINVAL, "sdd_mm must exceed sad_mm");
+    if (G->nu <= 0 || G->nv <= 0) return fail(PCR_EINVAL, "detector size must be > 0");
+    if ((double)G->nu * G->nv > 1.0e8) return fail(PCR_EINVAL, "detector too large");
+    if (!(G->du_mm > 0) || !(G->dv_mm > 0)) return fail(PCR_EINVAL, "pixel pitch must be > 0");
+    if (!(G->step_mm > 0)) return fail(PCR_EINVAL, "step_mm must be > 0");
+    double L = std::sqrt(G->sdd_mm * G->sdd_mm + 0.25 * (G->nu * G->du_mm) * (G->nu * G->du_mm) +
+                         0.25 * (G->nv * G->dv_mm) * (G->nv * G->dv_mm)) +
+               std::fabs(G->off_u_mm) + std::fabs(G->off_v_mm);
+    if (L / G->step_mm > 2.0e9) return fail(PCR_EINVAL, "too many samples per ray");
+    return PCR_OK;
+}
+
+static pcr_status check_compute(pcr_dtype d)
+{
+    if (d != PCR_F32 && d != PCR_F64) return fail(PCR_EINVAL, "compute dtype must be F32 or F64");
+    return PCR_OK;
+}
+
+static pcr_status check_storage(pcr_dtype d)
+{
+    if (dtype_size(d) == 0) return fail(PCR_EINVAL, "unknown dtype %d", (int)d);
+    return PCR_OK;
+}
+
+static pcr_status check_model(const pcr_model* m)
+{
+    if (!m) return fail(PCR_EINVAL, "model is NULL");
+    if (m->K < 1 || m->K > 8) return fail(PCR_EINVAL, "model K = %d must be in 1..8", m->K);
+    PCR_TRY(check_storage(m->storage));
+    if (!m->mean || !m->U) return fail(PCR_EINVAL, "model fields are NULL");
+    if (m->scale)
+        for (int k = 0; k < m->K; ++k)
+            if (!std::isfinite(m->scale[k])) return fail(PCR_EINVAL, "model scale must be finite");
+    return PCR_OK;
+}
+
+static pcr_status check_finite(const double* v, int n, const char* what)
+{
+    if (!v) return fail(PCR_EINVAL, "%s is NULL", what);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return fail(PCR_EINVAL, "%s[%d] is not finite", what, i);
+    return PCR_OK;
+}
+
+static void effective_w(const pcr_model& m, const double* w, double* w_eff)
+{
+    for (int k = 0; k < m.K; ++k) w_eff[k] = w[k] * (m.scale ? m.scale[k] : 1.0);
+}
+
+static int channels_for(int kc)
+{
+    return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+}
+
+// ------------------------------------------------------- device scratch --
+// Grow-only device buffer owned by the library.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+    pcr_status ensure(size_t need, int dev, hipStream_t s)
+    {
+        need = (need + 255) & ~(size_t)255;
+        if (p && bytes >= need && device == dev) return PCR_OK;
+        if (p) {
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipFree(p));
+            p = nullptr;
+            bytes = 0;
+        }
+        HIP_TRY(hipMalloc(&p, need));
+        bytes = need;
+        device = dev;
+        return PCR_OK;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct HostBuf {
+    double* p = nullptr;
+    size_t n = 0;
+    pcr_status ensure(size_t need)
+    {
+        if (p && n >= need) return PCR_OK;
+        if (p) HIP_TRY(hipHostFree(p));
+        p = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault));
+        n = need;
+        return PCR_OK;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// Per-thread scratch of the stateless entry points.
+struct TlsScratch {
+    DevBuf pad, small;
+    HostBuf host;
+    ~TlsScratch()
+    {
+        pad.release();
+        small.release();
+        host.release();
+    }
+};
+static thread_local TlsScratch tls;
+
+static pcr_status current_device(int* dev)
+{
+    HIP_TRY(hipGetDevice(dev));
+    return PCR_OK;
+}
+
+// ============================================================ C ABI =======
+extern "C" {
+
+const char* pcr_version(void) { return PCR_VERSION_STRING; }
+const char* pcr_last_error(void) { return g_err.c_str(); }
+
+void pcr_solve_opts_default(pcr_solve_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->max_iter = 50;
+    o->max_backtracks = 30;
+    o->sigma = 1e-4;
+    o->beta = 0.5;
+    o->eps_g = 1e-4;
+    o->step0 = 1.0;
+    o->fixed_mu = 0.0;
+    o->grad_mode = PCR_GRAD_FUSED;
+    o->localize = 0;
+    o->fp_tol_mm = 1e-6;
+    o->fp_max_iter = 200;
+}
+
+pcr_status pcr_dvf_compose(const pcr_grid* grid, const pcr_model* model, const double* w_host,
+                           pcr_dtype compute, void* dvf_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_model(model));
+    PCR_TRY(check_compute(compute));
+    PCR_TRY(check_finite(w_host, model->K, "w"));
+    if (!dvf_dev) return fail(PCR_EINVAL, "dvf_dev is NULL");
+    double w_eff[8];
+    effective_w(*model, w_host, w_eff);
+    HIP_TRY(launch_compose(compute, model->storage, *grid, model->K, model->mean, model->U, w_eff,
+                           dvf_dev, (hipStream_t)stream));
+    return PCR_OK;
+}
+
+pcr_status pcr_warp_volume(const pcr_grid* grid, pcr_dtype f0_dtype, const void* f0_dev,
+                           pcr_dtype compute, const void* dvf_dev, void* f_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_storage(f0_dtype));
+    PCR_TRY(check_compute(compute));
+    if (!f0_dev || !dvf_dev || !f_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    if (f_dev == f0_dev) return fail(PCR_EINVAL, "f_dev must not alias f0_dev");
+    HIP_TRY(launch_warp_plain(compute, f0_dtype, *grid, f0_dev, dvf_dev, f_dev, (hipStream_t)stream));
+    return PCR_OK;
+}
+
+pcr_status pcr_warp_adjoint(const pcr_grid* grid, pcr_dtype compute, const void* dvf_dev,
+                            const void* g_dev, void* out_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_compute(compute));
+    if (!dvf_dev || !g_dev || !out_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_zero(out_dev, N * dtype_size(compute), s));
+    HIP_TRY(launch_warp_adjoint(compute, *grid, dvf_dev, g_dev, out_dev, s));
+    return PCR_OK;
+}
+
+pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_dtype compute,
+                               const void* vol_dev, void* proj_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_geom(geom));
+    PCR_TRY(check_compute(compute));
+    if (!vol_dev || !proj_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    int dev;
+    PCR_TRY(current_device(&dev));
+    PadLayout L = make_pad(*grid, 1);
+    size_t bytes = L.cells() * dtype_size(compute);
+    PCR_TRY(tls.pad.ensure(bytes, dev, s));
+    HIP_TRY(launch_zero(tls.pad.p, bytes, s));
+    HIP_TRY(launch_pad(compute, L, vol_dev, tls.pad.p, s));
+    RayGeom rg = make_ray_geom(*grid, *geom);
+    MarchShape ms = choose_march_shape(rg);
+    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, s));
+    return PCR_OK;
+}
+
+pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom, pcr_dtype compute,
+                                    const void* resid_dev, void* vol_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_geom(geom));
+    PCR_TRY(check_compute(compute));
+    if (!resid_dev || !vol_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    int dev;
+    PCR_TRY(current_device(&dev));
+    PadLayout L = make_pad(*grid, 1);
+    size_t bytes = L.cells() * dtype_size(compute);
+    PCR_TRY(tls.pad.ensure(bytes, dev, s));
+    HIP_TRY(launch_zero(tls.pad.p, bytes, s));
+    RayGeom rg = make_ray_geom(*grid, *geom);
+    MarchShape ms = choose_march_shape(rg);
+    HIP_TRY(launch_backproject(compute, L, rg, ms, resid_dev, nullptr, nullptr, 0.0, 0.0, 1.0,
+                               tls.pad.p, s));
+    HIP_TRY(launch_unpad(compute, L, tls.pad.p, vol_dev, s));
+    return PCR_OK;
+}
+
+pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model, const double* w_host,
+                              const double p_ref_mm[3], double tol_mm, int32_t max_iter,
+                              double p_out_mm[3], int32_t* iters, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_model(model));
+    PCR_TRY(check_finite(w_host, model->K, "w"));
+    PCR_TRY(check_finite(p_ref_mm, 3, "p_ref_mm"));
+    if (!p_out_mm) return fail(PCR_EINVAL, "p_out_mm is NULL");
+    if (!(tol_mm > 0) || max_iter < 1) return fail(PCR_EINVAL, "need tol_mm > 0 and max_iter >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    int dev;
+    PCR_TRY(current_device(&dev));
+    PCR_TRY(tls.small.ensure(8 * sizeof(double), dev, s));
+    PCR_TRY(tls.host.ensure(8));
+    double w_eff[8];
+    effective_w(*model, w_host, w_eff);
+    HIP_TRY(launch_localize(model->storage, *grid, model->K, model->mean, model->U, w_eff, p_ref_mm,
+                            tol_mm, max_iter, (double*)tls.small.p, s));
+    HIP_TRY(hipMemcpyAsync(tls.host.p, tls.small.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int a = 0; a < 3; ++a) p_out_mm[a] = tls.host.p[a];
+    if (iters) *iters = (int32_t)tls.host.p[3];
+    if (tls.host.p[4] != 1.0) return fail(PCR_EDIVERGE, "fixed point did not converge in %d iterations", max_iter);
+    return PCR_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ context =====
+struct pcr_ctx {
+    pcr_grid grid;
+    pcr_model model;
+    double scale[8];
+    pcr_dtype f0_dtype, compute;
+    const void* f0;
+    int device;
+    PadLayout Lc, L1;     // fused (K+1 channels) and single-channel layouts
+    DevBuf volc, vol1, acc1, p, partials, moments;
+    HostBuf host;
+    ~pcr_ctx()
+    {
+        volc.release();
+        vol1.release();
+        acc1.release();
+        p.release();
+        partials.release();
+        moments.release();
+        host.release();
+    }
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && (prev == dev || hipSetDevice(dev) == hipSuccess)) ok = true;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Moments {
+    double m[kMaxMoments];
+    double M;
+    int K;
+    // J(a, b) = sum (p - a y - b)^2 expanded in the moments (eq. (2))
+    double J(double a, double b) const
+    {
+        return m[4] - 2 * a * m[3] - 2 * b * m[2] + a * a * m[1] + 2 * a * b * m[0] + b * b * M;
+    }
+    // dJ/dw_eff_k = 2 sum (p - a y - b) t_k (gradient of section 2.2)
+    double grad(int k, double a, double b) const
+    {
+        return 2.0 * (m[5 + 3 * k] - a * m[6 + 3 * k] - b * m[7 + 3 * k]);
+    }
+    // step 2, eq. (4): least-squares (a, b) for Y = [y, 1]; singular Y^T Y
+    // (constant y) gives a = 0 and b = mean(p)
+    void step2(double* a, double* b) const
+    {
+        double sy = m[0], syy = m[1], sp = m[2], syp = m[3];
+        double D = syy * M - sy * sy;
+        if (!(D > 1e-12 * syy * M)) {
+            *a = 0.0;
+            *b = M > 0 ? sp / M : 0.0;
+            return;
+        }
+        *a = (M * syp - sy * sp) / D;
+        *b = (syy * sp - sy * syp) / D;
+    }
+};
+
+struct Solver {
+    pcr_ctx* c;
+    hipStream_t s;
+    RayGeom rg;
+    MarchShape ms;
+    int M;
+    int blocks;
+    const void* y;
+
+    pcr_status prepare(const void* y_, const pcr_geom& G, int mode)
+    {
+        y = y_;
+        rg = make_ray_geom(c->grid, G);
+        ms = choose_march_shape(rg);
+        M = G.nu * G.nv;
+        blocks = march_blocks(rg, ms);
+        int cblocks = contract_blocks(c->grid);
+        PCR_TRY(c->partials.ensure((size_t)std::max(blocks, cblocks) * kMaxMoments * sizeof(double),
+                                   c->device, s));
+        PCR_TRY(c->moments.ensure(kMaxMoments * sizeof(double), c->device, s));
+        PCR_TRY(c->host.ensure(kMaxMoments));
+        size_t esz = c->compute == PCR_F64 ? 8 : 4;
+        if (mode == PCR_GRAD_ADJOINT) {
+            size_t b1 = c->L1.cells() * esz;
+            bool fresh = c->vol1.p == nullptr;
+            PCR_TRY(c->vol1.ensure(b1, c->device, s));
+            if (fresh) HIP_TRY(launch_zero(c->vol1.p, c->vol1.bytes, s));
+            PCR_TRY(c->acc1.ensure(b1, c->device, s));
+            PCR_TRY(c->p.ensure((size_t)M * esz, c->device, s));
+        }
+        return PCR_OK;
+    }
+
+    // One projection of a trial w: moments of (f, h_1..h_K) (fused) or of f
+    // alone with p kept for the adjoint (adjoint).
+    pcr_status eval(const double* w, int mode, Moments& out)
+    {
+        double w_eff[8];
+        effective_w(c->model, w, w_eff);
+        const int K = c->model.K;
+        int kc, stride;
+        if (mode == PCR_GRAD_FUSED) {
+            kc = K + 1;
+            stride = 5 + 3 * (c->Lc.C - 1);
+            HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->Lc, K,
+                                      true, c->f0, c->model.mean, c->model.U, w_eff, c->volc.p, s));
+            HIP_TRY(launch_march(c->compute, c->Lc, kc, rg, ms, c->volc.p, y, nullptr,
+                                 (double*)c->partials.p, s));
+        } else {
+            kc = 1;
+            stride = 5;
+            HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1, K,
+                                      false, c->f0, c->model.mean, c->model.U, w_eff, c->vol1.p, s));
+            HIP_TRY(launch_march(c->compute, c->L1, 1, rg, ms, c->vol1.p, y, c->p.p,
+                                 (double*)c->partials.p, s));
+        }
+        int nm = n_moments(kc);
+        HIP_TRY(launch_reduce((const double*)c->partials.p, blocks, stride, nm, (double*)c->moments.p, s));
+        HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, nm * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::memset(out.m, 0, sizeof out.m);
+        std::memcpy(out.m, c->host.p, nm * sizeof(double));
+        out.M = (double)M;
+        out.K = K;
+        return PCR_OK;
+    }
+
+    // Gradient at the w of the last adjoint eval (its p is in c->p):
+    // g = P^T (2 (p - a y - b)), then sum_v g (df/dx) . u_k.
+    pcr_status grad_adjoint(const double* w, double a, double b, double* grad)
+    {
+        double w_eff[8];
+        effective_w(c->model, w, w_eff);
+        const int K = c->model.K;
+        HIP_TRY(launch_zero(c->acc1.p, c->acc1.bytes, s));
+        HIP_TRY(launch_backproject(c->compute, c->L1, rg, ms, nullptr, c->p.p, y, a, b, 2.0,
+                                   c->acc1.p, s));
+        HIP_TRY(launch_contract(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1, K, c->f0,
+                                c->model.mean, c->model.U, w_eff, c->acc1.p,
+                                (double*)c->partials.p, s));
+        HIP_TRY(launch_reduce((const double*)c->partials.p, contract_blocks(c->grid), 8, K,
+                              (double*)c->moments.p, s));
+        HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < K; ++k) grad[k] = c->host.p[k];
+        return PCR_OK;
+    }
+
+    // Cost and gradient in w (with the model scales) at (a, b).
+    pcr_status cost_grad_at(const double* w, const Moments& mo, int mode, double a, double b,
+                            double* J, double* grad)
+    {
+        const int K = c->model.K;
+        *J = mo.J(a, b);
+        if (mode == PCR_GRAD_FUSED) {
+            for (int k = 0; k < K; ++k) grad[k] = mo.grad(k, a, b);
+        } else {
+            PCR_TRY(grad_adjoint(w, a, b, grad));
+        }
+        for (int k = 0; k < K; ++k) grad[k] *= c->model.scale ? c->scale[k] : 1.0;
+        return PCR_OK;
+    }
+};
+
+static pcr_status check_opts(const pcr_solve_opts* o, int K)
+{
+    if (!o) return fail(PCR_EINVAL, "opts is NULL");
+    if (o->max_iter < 0 || o->max_backtracks < 1) return fail(PCR_EINVAL, "bad iteration limits");
+    if (!(o->sigma > 0 && o->sigma < 1)) return fail(PCR_EINVAL, "sigma must be in (0, 1)");
+    if (!(o->beta > 0 && o->beta < 1)) return fail(PCR_EINVAL, "beta must be in (0, 1)");
+    if (!(o->eps_g >= 0) || !std::isfinite(o->eps_g)) return fail(PCR_EINVAL, "bad eps_g");
+    if (!(o->fixed_mu >= 0) || !std::isfinite(o->fixed_mu)) return fail(PCR_EINVAL, "bad fixed_mu");
+    if (o->fixed_mu == 0 && !(o->step0 > 0 && std::isfinite(o->step0)))
+        return fail(PCR_EINVAL, "step0 must be > 0");
+    if (o->grad_mode != PCR_GRAD_FUSED && o->grad_mode != PCR_GRAD_ADJOINT)
+        return fail(PCR_EINVAL, "unknown grad_mode %d", o->grad_mode);
+    if (o->localize) {
+        PCR_TRY(check_finite(o->p_ref_mm, 3, "p_ref_mm"));
+        if (!(o->fp_tol_mm > 0) || o->fp_max_iter < 1) return fail(PCR_EINVAL, "bad fixed-point options");
+    }
+    (void)K;
+    return PCR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtype f0_dtype,
+                          const void* f0_dev, pcr_dtype compute, pcr_ctx** out)
+{
+    if (!out) return fail(PCR_EINVAL, "out is NULL");
+    *out = nullptr;
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_model(model));
+    PCR_TRY(check_storage(f0_dtype));
+    PCR_TRY(check_compute(compute));
+    if (!f0_dev) return fail(PCR_EINVAL, "f0_dev is NULL");
+    pcr_ctx* c = new (std::nothrow) pcr_ctx();
+    if (!c) return fail(PCR_ENOMEM, "host allocation failed");
+    c->grid = *grid;
+    c->model = *model;
+    for (int k = 0; k < 8; ++k) c->scale[k] = (model->scale && k < model->K) ? model->scale[k] : 1.0;
+    c->model.scale = model->scale ? c->scale : nullptr;
+    c->f0_dtype = f0_dtype;
+    c->compute = compute;
+    c->f0 = f0_dev;
+    pcr_status st = current_device(&c->device);
+    if (st != PCR_OK) {
+        delete c;
+        return st;
+    }
+    c->Lc = make_pad(*grid, channels_for(model->K + 1));
+    c->L1 = make_pad(*grid, 1);
+    size_t esz = compute == PCR_F64 ? 8 : 4;
+    st = c->volc.ensure(c->Lc.cells() * c->Lc.C * esz, c->device, nullptr);
+    if (st == PCR_OK) {
+        hipError_t e = launch_zero(c->volc.p, c->volc.bytes, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = fail(PCR_EDEVICE, "zeroing context scratch: %s", hipGetErrorString(e));
+    }
+    if (st != PCR_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return PCR_OK;
+}
+
+void pcr_ctx_destroy(pcr_ctx* ctx)
+{
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+size_t pcr_ctx_device_bytes(const pcr_ctx* c)
+{
+    if (!c) return 0;
+    return c->volc.bytes + c->vol1.bytes + c->acc1.bytes + c->p.bytes + c->partials.bytes +
+           c->moments.bytes;
+}
+
+pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
+                         const double* w_host, double a, double b, int32_t grad_mode,
+                         double* cost_host, double* grad_host, void* stream)
+{
+    if (!ctx) return fail(PCR_EINVAL, "ctx is NULL");
+    PCR_TRY(check_geom(geom));
+    PCR_TRY(check_finite(w_host, ctx->model.K, "w"));
+    if (!std::isfinite(a) || !std::isfinite(b)) return fail(PCR_EINVAL, "a, b must be finite");
+    if (!y_dev || !cost_host || !grad_host) return fail(PCR_EINVAL, "NULL pointer");
+    if (grad_mode != PCR_GRAD_FUSED && grad_mode != PCR_GRAD_ADJOINT)
+        return fail(PCR_EINVAL, "unknown grad_mode %d", grad_mode);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->device);
+    Solver S{ctx, (hipStream_t)stream};
+    PCR_TRY(S.prepare(y_dev, *geom, grad_mode));
+    Moments mo;
+    PCR_TRY(S.eval(w_host, grad_mode, mo));
+    PCR_TRY(S.cost_grad_at(w_host, mo, grad_mode, a, b, cost_host, grad_host));
+    return PCR_OK;
+}
+
+pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
+                                           const pcr_solve_opts* opts, double* w_inout,
+                                           double* ab_out, pcr_solve_stats* stats, void* stream)
+{
+    if (!ctx) return fail(PCR_EINVAL, "ctx is NULL");
+    PCR_TRY(check_geom(geom));
+    const int K = ctx->model.K;
+    PCR_TRY(check_opts(opts, K));
+    PCR_TRY(check_finite(w_inout, K, "w_inout"));
+    if (!y_dev) return fail(PCR_EINVAL, "y_dev is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->device);
+    const int mode = opts->grad_mode;
+    const bool fixed = opts->fixed_mu > 0;
+    Solver S{ctx, (hipStream_t)stream};
+    PCR_TRY(S.prepare(y_dev, *geom, mode));
+
+    double w[8], wt[8], g[8], a, b, J;
+    for (int k = 0; k < K; ++k) w[k] = w_inout[k];
+    Moments mo, mt;
+    PCR_TRY(S.eval(w, mode, mo));
+    mo.step2(&a, &b);
+    PCR_TRY(S.cost_grad_at(w, mo, mode, a, b, &J, g));
+    auto norm = [K](const double* v) {
+        double s = 0;
+        for (int k = 0; k < K; ++k) s += v[k] * v[k];
+        return std::sqrt(s);
+    };
+    double gn = norm(g), g0 = gn, J0 = J;
+    double mu = fixed ? opts->fixed_mu : (g0 > 0 ? opts->step0 / g0 : 0.0);
+    pcr_status status = PCR_OK;
+    int iters = 0, trials = 0;
+    for (int n = 0;; ++n) {
+        if (!std::isfinite(J) || !std::isfinite(gn)) {
+            status = fail(PCR_EDEVICE, "non-finite cost or gradient (input contains NaN/Inf?)");
+            break;
+        }
+        if (gn <= opts->eps_g * g0) break;
+        if (n == opts->max_iter) {
+            status = PCR_ENOCONV;
+            break;
+        }
+        bool accepted = false;
+        for (int l = 0; l < (fixed ? 1 : opts->max_backtracks); ++l) {
+            for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * g[k];
+            PCR_TRY(S.eval(wt, mode, mt));
+            ++trials;
+            if (fixed || mt.J(a, b) <= J - opts->sigma * mu * gn * gn) {
+                accepted = true;
+                break;
+            }
+            mu *= opts->beta;
+        }
+        if (!accepted) {
+            status = PCR_ENOCONV;
+            break;
+        }
+        for (int k = 0; k < K; ++k) w[k] = wt[k];
+        mo = mt;
+        mo.step2(&a, &b);
+        PCR_TRY(S.cost_grad_at(w, mo, mode, a, b, &J, g));
+        gn = norm(g);
+        iters = n + 1;
+        if (!fixed) mu /= opts->beta;
+    }
+    if (status == PCR_ENOCONV) fail(PCR_ENOCONV, "no convergence: %d iterations, %d trials", iters, trials);
+    for (int k = 0; k < K; ++k) w_inout[k] = w[k];
+    if (ab_out) {
+        ab_out[0] = a;
+        ab_out[1] = b;
+    }
+    pcr_solve_stats st{};
+    st.status = status;
+    st.iterations = iters;
+    st.trials = trials;
+    st.J0 = J0;
+    st.J = J;
+    st.gnorm0 = g0;
+    st.gnorm = gn;
+    st.a = a;
+    st.b = b;
+    st.fp_status = PCR_OK;
+    if (opts->localize && (status == PCR_OK || status == PCR_ENOCONV)) {
+        pcr_status ls = pcr_localize_tumor(&ctx->grid, &ctx->model, w, opts->p_ref_mm, opts->fp_tol_mm,
+                                           opts->fp_max_iter, st.tumor_mm, &st.fp_iterations, stream);
+        st.fp_status = ls;
+        if (ls != PCR_OK && ls != PCR_EDIVERGE) return ls;
+    }
+    if (stats) *stats = st;
+    return status;
+}
+
+}  // extern "C"

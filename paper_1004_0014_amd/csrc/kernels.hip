@@ -1,0 +1,928 @@
+// HIP kernels for gfx950 (MI355X, CDNA4, wave64).
+//
+// Hot path of single-projection reconstruction under a PCA motion model
+// (Li et al., section 2.2): per iteration compose the DVF, warp the
+// reference image, ray-march the cone-beam projection, form the residual and
+// return the cost and its gradient in w.
+//
+//  * Voxel passes (compose, warp, contraction) stream HBM: one thread per
+//    voxel, x-contiguous lanes, structure-of-arrays fields.
+//  * The ray march gathers from a zero-padded, channel-interleaved copy of
+//    the warped image that stays resident in L2/MALL; each lane marches one
+//    ray (or one segment of one) so a wave's taps fall in a compact 3-D
+//    region; samples are clamped to the interpolant's support so no tap
+//    needs a bounds check.
+//  * Detector-wide and volume-wide sums accumulate in FP64: wave shuffles,
+//    then LDS, then per-block partials, then one fixed-order final pass, so
+//    every result is bitwise reproducible (no floating-point atomics in any
+//    reduction).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <algorithm>
+#include <cstdint>
+
+#include "pcr_internal.h"
+
+namespace pcr {
+
+// ------------------------------------------------------------ storage ----
+struct bf16 {
+    uint16_t bits;
+};
+
+template <typename R, typename S>
+__device__ __forceinline__ R widen(S v);
+template <> __device__ __forceinline__ float widen<float, float>(float v) { return v; }
+template <> __device__ __forceinline__ double widen<double, float>(float v) { return v; }
+template <> __device__ __forceinline__ float widen<float, double>(double v) { return (float)v; }
+template <> __device__ __forceinline__ double widen<double, double>(double v) { return v; }
+template <> __device__ __forceinline__ float widen<float, bf16>(bf16 v)
+{
+    return __uint_as_float((uint32_t)v.bits << 16);
+}
+template <> __device__ __forceinline__ double widen<double, bf16>(bf16 v)
+{
+    return (double)__uint_as_float((uint32_t)v.bits << 16);
+}
+template <> __device__ __forceinline__ float widen<float, _Float16>(_Float16 v) { return (float)v; }
+template <> __device__ __forceinline__ double widen<double, _Float16>(_Float16 v) { return (double)(float)v; }
+
+template <typename R, int C>
+struct alignas((sizeof(R) * C) >= 16 ? 16 : (sizeof(R) * C)) Chan {
+    R v[C];
+};
+
+template <typename T>
+__device__ __forceinline__ T clampv(T x, T lo, T hi)
+{
+    return fmin(fmax(x, lo), hi);
+}
+__device__ __forceinline__ float clampv(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+
+// ----------------------------------------------------------- reductions --
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block (256 threads = 4 waves) sum of NM doubles per thread; thread t < nm
+// writes dst[t].  Fixed order: wave tree, then waves 0..3.
+template <int NM>
+__device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double* dst)
+{
+    __shared__ double red[4][NM];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        double s = wave_sum(m[i]);
+        if (lane == 0) red[wv][i] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nm) {
+        double s = red[0][threadIdx.x];
+        s += red[1][threadIdx.x];
+        s += red[2][threadIdx.x];
+        s += red[3][threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ part, int nblocks,
+                                                int stride, int nm, double* __restrict__ out)
+{
+    __shared__ double buf[256];
+    for (int m = 0; m < nm; ++m) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) s += part[(size_t)b * stride + m];
+        buf[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[m] = buf[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ compose ----
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) k_compose(const S* __restrict__ mean,
+                                                 const S* __restrict__ U, int K, size_t N,
+                                                 Chan<double, 8> w, R* __restrict__ dvf)
+{
+    size_t v = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= N) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R x = widen<R>(mean[a * N + v]);
+        for (int k = 0; k < K; ++k) x += (R)w.v[k] * widen<R>(U[(size_t)(k * 3 + a) * N + v]);
+        dvf[a * N + v] = x;
+    }
+}
+
+// --------------------------------------------------------------- warp ----
+// Trilinear sample of an unpadded image at index-space point q, zero outside;
+// optionally also the exact partial derivatives dT/dq (floor cell).
+template <typename R, typename S, bool GRAD>
+__device__ __forceinline__ R sample_f0(const S* __restrict__ f0, int nx, int ny, int nz,
+                                       R qx, R qy, R qz, R* dT)
+{
+    qx = clampv(qx, (R)-2, (R)(nx + 1));
+    qy = clampv(qy, (R)-2, (R)(ny + 1));
+    qz = clampv(qz, (R)-2, (R)(nz + 1));
+    R fx = floor(qx), fy = floor(qy), fz = floor(qz);
+    int i0 = (int)fx, j0 = (int)fy, k0 = (int)fz;
+    R ax = qx - fx, ay = qy - fy, az = qz - fz;
+    R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
+    R c[2][2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                int i = i0 + dx, j = j0 + dy, k = k0 + dz;
+                bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny &&
+                          (unsigned)k < (unsigned)nz;
+                c[dz][dy][dx] = in ? widen<R>(f0[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)])
+                                   : (R)0;
+            }
+    R w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
+    R val = w00 * (bx * c[0][0][0] + ax * c[0][0][1]) + w10 * (bx * c[0][1][0] + ax * c[0][1][1]) +
+            w01 * (bx * c[1][0][0] + ax * c[1][0][1]) + w11 * (bx * c[1][1][0] + ax * c[1][1][1]);
+    if (GRAD) {
+        dT[0] = w00 * (c[0][0][1] - c[0][0][0]) + w10 * (c[0][1][1] - c[0][1][0]) +
+                w01 * (c[1][0][1] - c[1][0][0]) + w11 * (c[1][1][1] - c[1][1][0]);
+        dT[1] = bx * bz * (c[0][1][0] - c[0][0][0]) + ax * bz * (c[0][1][1] - c[0][0][1]) +
+                bx * az * (c[1][1][0] - c[1][0][0]) + ax * az * (c[1][1][1] - c[1][0][1]);
+        dT[2] = bx * by * (c[1][0][0] - c[0][0][0]) + ax * by * (c[1][0][1] - c[0][0][1]) +
+                bx * ay * (c[1][1][0] - c[0][1][0]) + ax * ay * (c[1][1][1] - c[0][1][1]);
+    }
+    return val;
+}
+
+struct VoxGrid {
+    int nx, ny, nz;
+    double sp[3];
+};
+
+// Standalone warp: f[v] = T[f0](v + dvf[v] / s).
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) k_warp_plain(const S* __restrict__ f0,
+                                                    const R* __restrict__ dvf, VoxGrid g,
+                                                    R* __restrict__ f)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    size_t N = (size_t)g.nx * g.ny * g.nz;
+    size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+    R qx = (R)i + dvf[v] / (R)g.sp[0];
+    R qy = (R)j + dvf[N + v] / (R)g.sp[1];
+    R qz = (R)k + dvf[2 * N + v] / (R)g.sp[2];
+    f[v] = sample_f0<R, S, false>(f0, g.nx, g.ny, g.nz, qx, qy, qz, nullptr);
+}
+
+// Fused compose + warp (+ tangents) into the padded multi-channel layout.
+template <typename R, typename S, typename F, int C, bool TAN>
+__global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
+                                                    const S* __restrict__ mean,
+                                                    const S* __restrict__ U, int K,
+                                                    Chan<double, 8> w, VoxGrid g, int px, int py,
+                                                    Chan<R, C>* __restrict__ out)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    size_t N = (size_t)g.nx * g.ny * g.nz;
+    size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+    R x[3];
+    R u[TAN ? 8 : 1][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = widen<R>(mean[a * N + v]);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        if (kk < K) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R uv = widen<R>(U[(size_t)(kk * 3 + a) * N + v]);
+                x[a] += (R)w.v[kk] * uv;
+                if (TAN) u[TAN ? kk : 0][a] = uv;
+            }
+        }
+    }
+    R qx = (R)i + x[0] / (R)g.sp[0];
+    R qy = (R)j + x[1] / (R)g.sp[1];
+    R qz = (R)k + x[2] / (R)g.sp[2];
+    R dT[3];
+    Chan<R, C> o;
+#pragma unroll
+    for (int c = 0; c < C; ++c) o.v[c] = (R)0;
+    o.v[0] = sample_f0<R, F, TAN>(f0, g.nx, g.ny, g.nz, qx, qy, qz, dT);
+    if (TAN) {
+        R G0 = dT[0] / (R)g.sp[0], G1 = dT[1] / (R)g.sp[1], G2 = dT[2] / (R)g.sp[2];
+#pragma unroll
+        for (int kk = 0; kk < C - 1; ++kk)
+            if (kk < K) o.v[kk + 1] = G0 * u[TAN ? kk : 0][0] + G1 * u[TAN ? kk : 0][1] + G2 * u[TAN ? kk : 0][2];
+    }
+    size_t pc = (size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1));
+    out[pc] = o;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_pad(const R* __restrict__ vol, VoxGrid g, int px, int py,
+                                             R* __restrict__ pad)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+    pad[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))] = vol[v];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_unpad(const R* __restrict__ pad, VoxGrid g, int px,
+                                               int py, R* __restrict__ vol)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+    vol[v] = pad[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))];
+}
+
+__global__ void __launch_bounds__(256) k_zero16(uint4* __restrict__ p, size_t n16)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i < n16; i += (size_t)gridDim.x * 256) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_zero4(uint32_t* __restrict__ p, size_t n4)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i < n4; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+// ---------------------------------------------------------- ray march ----
+template <typename R>
+struct RaySeg {
+    R q0[3];         // index-space point of the segment's first sample
+    R dq[3];         // index-space step per sample
+    int count;       // samples in the segment
+};
+
+// Sample range of ray (iu, iv) on the global grid t = n dt, clipped to the
+// support box [-1, n_a] of the interpolant (widened by one sample at each
+// end: samples outside the support are clamped onto zero cells), then split
+// into `seg` equal segments.  FP64, once per ray.
+template <typename R>
+__device__ __forceinline__ RaySeg<R> ray_segment(const RayGeom& g, int iu, int iv, int seg, int sid)
+{
+    RaySeg<R> r;
+    double u = g.u0 + iu * g.du, v = g.v0 + iv * g.dv;
+    double D[3], L2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D[a] = g.qc[a] + u * g.eu[a] + v * g.ev[a] - g.qs[a];
+        double w = D[a] * g.sp[a];
+        L2 += w * w;
+    }
+    double L = sqrt(L2);
+    double tmin = 0.0, tmax = L, dq[3];
+    bool hit = L > 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dq[a] = D[a] / L;
+        if (dq[a] != 0.0) {
+            double t1 = (-1.0 - g.qs[a]) / dq[a], t2 = (g.lim[a] - g.qs[a]) / dq[a];
+            tmin = fmax(tmin, fmin(t1, t2));
+            tmax = fmin(tmax, fmax(t1, t2));
+        } else if (!(g.qs[a] > -1.0 && g.qs[a] < g.lim[a])) {
+            hit = false;
+        }
+    }
+    r.count = 0;
+    if (!hit || !(tmin <= tmax)) {
+        r.q0[0] = r.q0[1] = r.q0[2] = (R)0;
+        r.dq[0] = r.dq[1] = r.dq[2] = (R)0;
+        return r;
+    }
+    long nlast = (long)floor(L / g.dt);
+    long n0 = (long)ceil(tmin / g.dt) - 1, n1 = (long)floor(tmax / g.dt) + 1;
+    if (n0 < 0) n0 = 0;
+    if (n1 > nlast) n1 = nlast;
+    long cnt = n1 - n0 + 1;
+    if (cnt < 0) cnt = 0;
+    long m0 = cnt * sid / seg, m1 = cnt * (sid + 1) / seg;
+    r.count = (int)(m1 - m0);
+    double t0 = (double)(n0 + m0) * g.dt;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.q0[a] = (R)(g.qs[a] + t0 * dq[a]);
+        r.dq[a] = (R)(g.dt * dq[a]);
+    }
+    return r;
+}
+
+__device__ __forceinline__ void ray_of_thread(const MarchShape& ms, int tiles_u, int& iu, int& iv,
+                                              int& sid, int& rloc)
+{
+    const int rpb = 256 / ms.seg;
+    rloc = threadIdx.x % rpb;
+    sid = threadIdx.x / rpb;
+    const int tv_rows = rpb / ms.tile_u;
+    int tu = blockIdx.x % tiles_u, tv = blockIdx.x / tiles_u;
+    iu = tu * ms.tile_u + rloc % ms.tile_u;
+    iv = tv * tv_rows + rloc / ms.tile_u;
+}
+
+// Ray march over the padded image; p and moments per ray.
+template <typename R, int C>
+__global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int tiles_u,
+                                               const Chan<R, C>* __restrict__ vol, int px,
+                                               int py, float fnx, float fny, float fnz, int kc,
+                                               const R* __restrict__ y, R* __restrict__ p_out,
+                                               double* __restrict__ partials)
+{
+    int iu, iv, sid, rloc;
+    ray_of_thread(ms, tiles_u, iu, iv, sid, rloc);
+    const bool valid = iu < g.nu && iv < g.nv;
+    R acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = (R)0;
+    if (valid) {
+        RaySeg<R> rs = ray_segment<R>(g, iu, iv, ms.seg, sid);
+        const long pxy = (long)px * py;
+        const Chan<R, C>* base = vol + (1 + px + pxy);   // cell of voxel (0,0,0)
+        for (int m = 0; m < rs.count; ++m) {
+            R fm = (R)m;
+            R qx = clampv(fma(fm, rs.dq[0], rs.q0[0]), (R)-1, (R)fnx);
+            R qy = clampv(fma(fm, rs.dq[1], rs.q0[1]), (R)-1, (R)fny);
+            R qz = clampv(fma(fm, rs.dq[2], rs.q0[2]), (R)-1, (R)fnz);
+            R flx = floor(qx), fly = floor(qy), flz = floor(qz);
+            int ix = (int)flx, iy = (int)fly, iz = (int)flz;
+            R ax = qx - flx, ay = qy - fly, az = qz - flz;
+            R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
+            R w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
+            const Chan<R, C>* c0 = base + ((long)ix + (long)px * iy + pxy * iz);
+            Chan<R, C> t000 = c0[0], t100 = c0[1], t010 = c0[px], t110 = c0[px + 1];
+            Chan<R, C> t001 = c0[pxy], t101 = c0[pxy + 1], t011 = c0[pxy + px],
+                       t111 = c0[pxy + px + 1];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                R x00 = bx * t000.v[c] + ax * t100.v[c];
+                R x10 = bx * t010.v[c] + ax * t110.v[c];
+                R x01 = bx * t001.v[c] + ax * t101.v[c];
+                R x11 = bx * t011.v[c] + ax * t111.v[c];
+                acc[c] += w00 * x00 + w10 * x10 + w01 * x01 + w11 * x11;
+            }
+        }
+    }
+    if (ms.seg > 1) {
+        __shared__ R segbuf[256 * C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
+        __syncthreads();
+        if (sid == 0) {
+            const int rpb = 256 / ms.seg;
+            for (int s = 1; s < ms.seg; ++s)
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s * rpb) * C + c];
+        }
+    }
+    const bool owner = valid && sid == 0;
+    const R dt = (R)g.dt;
+    if (owner && p_out) p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
+    if (partials) {
+        constexpr int NM = 5 + 3 * (C - 1);
+        double m[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) m[i] = 0.0;
+        if (owner) {
+            double yd = (double)y[iu + (size_t)g.nu * iv];
+            double pd = (double)(dt * acc[0]);
+            m[0] = yd;
+            m[1] = yd * yd;
+            m[2] = pd;
+            m[3] = yd * pd;
+            m[4] = pd * pd;
+#pragma unroll
+            for (int k = 0; k < C - 1; ++k) {
+                if (k + 1 < kc) {
+                    double tk = (double)(dt * acc[k + 1]);
+                    m[5 + 3 * k] = pd * tk;
+                    m[6 + 3 * k] = yd * tk;
+                    m[7 + 3 * k] = tk;
+                }
+            }
+        }
+        block_sum_store<NM>(m, 5 + 3 * (kc - 1), partials + (size_t)blockIdx.x * NM);
+    }
+}
+
+// Exact transpose of the single-channel march: scatter r * dt * weight.
+template <typename R>
+__global__ void __launch_bounds__(256) k_backproject(RayGeom g, MarchShape ms, int tiles_u,
+                                                     R* __restrict__ acc, int px, int py,
+                                                     float fnx, float fny, float fnz,
+                                                     const R* __restrict__ resid,
+                                                     const R* __restrict__ p,
+                                                     const R* __restrict__ y, double a, double b,
+                                                     double scale)
+{
+    int iu, iv, sid, rloc;
+    ray_of_thread(ms, tiles_u, iu, iv, sid, rloc);
+    if (iu >= g.nu || iv >= g.nv) return;
+    size_t pix = iu + (size_t)g.nu * iv;
+    R r;
+    if (resid)
+        r = resid[pix];
+    else
+        r = (R)(scale * ((double)p[pix] - a * (double)y[pix] - b));
+    if (r == (R)0) return;
+    const R rw = r * (R)g.dt;
+    RaySeg<R> rs = ray_segment<R>(g, iu, iv, ms.seg, sid);
+    const long pxy = (long)px * py;
+    R* base = acc + (1 + px + pxy);
+    for (int m = 0; m < rs.count; ++m) {
+        R fm = (R)m;
+        R qx = clampv(fma(fm, rs.dq[0], rs.q0[0]), (R)-1, (R)fnx);
+        R qy = clampv(fma(fm, rs.dq[1], rs.q0[1]), (R)-1, (R)fny);
+        R qz = clampv(fma(fm, rs.dq[2], rs.q0[2]), (R)-1, (R)fnz);
+        R flx = floor(qx), fly = floor(qy), flz = floor(qz);
+        int ix = (int)flx, iy = (int)fly, iz = (int)flz;
+        R ax = qx - flx, ay = qy - fly, az = qz - flz;
+        R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
+        R w00 = by * bz * rw, w10 = ay * bz * rw, w01 = by * az * rw, w11 = ay * az * rw;
+        R* c0 = base + ((long)ix + (long)px * iy + pxy * iz);
+        unsafeAtomicAdd(c0, bx * w00);
+        unsafeAtomicAdd(c0 + 1, ax * w00);
+        unsafeAtomicAdd(c0 + px, bx * w10);
+        unsafeAtomicAdd(c0 + px + 1, ax * w10);
+        unsafeAtomicAdd(c0 + pxy, bx * w01);
+        unsafeAtomicAdd(c0 + pxy + 1, ax * w01);
+        unsafeAtomicAdd(c0 + pxy + px, bx * w11);
+        unsafeAtomicAdd(c0 + pxy + px + 1, ax * w11);
+    }
+}
+
+// ---------------------------------------------------------- contraction --
+// partials[block][k] = sum_v g[v] * sum_a (1/s_a) dT[f0]/dq_a(q_v) u_k[a][v]
+template <typename R, typename S, typename F>
+__global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
+                                                  const S* __restrict__ mean,
+                                                  const S* __restrict__ U, int K,
+                                                  Chan<double, 8> w, VoxGrid g, int px, int py,
+                                                  const R* __restrict__ gpad,
+                                                  double* __restrict__ partials)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    double m[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) m[kk] = 0.0;
+    if (i < g.nx && j < g.ny) {
+        size_t N = (size_t)g.nx * g.ny * g.nz;
+        size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+        R gv = gpad[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))];
+        if (gv != (R)0) {
+            R x[3], u[8][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[a] = widen<R>(mean[a * N + v]);
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                if (kk < K)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        u[kk][a] = widen<R>(U[(size_t)(kk * 3 + a) * N + v]);
+                        x[a] += (R)w.v[kk] * u[kk][a];
+                    }
+            R qx = (R)i + x[0] / (R)g.sp[0];
+            R qy = (R)j + x[1] / (R)g.sp[1];
+            R qz = (R)k + x[2] / (R)g.sp[2];
+            R dT[3];
+            sample_f0<R, F, true>(f0, g.nx, g.ny, g.nz, qx, qy, qz, dT);
+            double G0 = (double)dT[0] / g.sp[0], G1 = (double)dT[1] / g.sp[1],
+                   G2 = (double)dT[2] / g.sp[2];
+            double gd = (double)gv;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                if (kk < K)
+                    m[kk] = gd * (G0 * (double)u[kk][0] + G1 * (double)u[kk][1] + G2 * (double)u[kk][2]);
+        }
+    }
+    // threadIdx is 2-D (64 x 4): flatten for the block reduction
+    __shared__ double red[4][8];
+    const int lane = threadIdx.x, wv = threadIdx.y;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        double s = wave_sum(m[kk]);
+        if (lane == 0) red[wv][kk] = s;
+    }
+    __syncthreads();
+    int t = threadIdx.x + 64 * threadIdx.y;
+    if (t < K) {
+        size_t blk = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+        partials[blk * 8 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    }
+}
+
+// -------------------------------------------------------- warp adjoint ---
+template <typename R>
+__global__ void __launch_bounds__(256) k_warp_adjoint(const R* __restrict__ dvf,
+                                                      const R* __restrict__ gv, VoxGrid g,
+                                                      R* __restrict__ out)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    size_t N = (size_t)g.nx * g.ny * g.nz;
+    size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
+    R val = gv[v];
+    if (val == (R)0) return;
+    R qx = (R)i + dvf[v] / (R)g.sp[0];
+    R qy = (R)j + dvf[N + v] / (R)g.sp[1];
+    R qz = (R)k + dvf[2 * N + v] / (R)g.sp[2];
+    qx = clampv(qx, (R)-2, (R)(g.nx + 1));
+    qy = clampv(qy, (R)-2, (R)(g.ny + 1));
+    qz = clampv(qz, (R)-2, (R)(g.nz + 1));
+    R fx = floor(qx), fy = floor(qy), fz = floor(qz);
+    int i0 = (int)fx, j0 = (int)fy, k0 = (int)fz;
+    R ax = qx - fx, ay = qy - fy, az = qz - fz;
+    R wx[2] = {(R)1 - ax, ax}, wy[2] = {(R)1 - ay, ay}, wz[2] = {(R)1 - az, az};
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                int ii = i0 + dx, jj = j0 + dy, kk = k0 + dz;
+                if ((unsigned)ii < (unsigned)g.nx && (unsigned)jj < (unsigned)g.ny &&
+                    (unsigned)kk < (unsigned)g.nz)
+                    unsafeAtomicAdd(out + ((size_t)ii + (size_t)g.nx * ((size_t)jj + (size_t)g.ny * kk)),
+                                    wx[dx] * wy[dy] * wz[dz] * val);
+            }
+}
+
+// ------------------------------------------------------------ localise ---
+// One wave: lane t < 8 owns trilinear corner t; FP64 throughout.
+template <typename S>
+__global__ void __launch_bounds__(64) k_localize(const S* __restrict__ mean,
+                                                 const S* __restrict__ U, int K,
+                                                 Chan<double, 8> w, VoxGrid g, double pr0,
+                                                 double pr1, double pr2, double org0, double org1,
+                                                 double org2, double tol, int max_iter,
+                                                 double* __restrict__ out)
+{
+    const int t = threadIdx.x;
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const double org[3] = {org0, org1, org2};
+    const double pref[3] = {pr0, pr1, pr2};
+    double p[3] = {pr0, pr1, pr2};
+    int it = 0, conv = 0;
+    for (it = 1; it <= max_iter; ++it) {
+        int i0[3];
+        double ph[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double q = (p[a] - org[a]) / g.sp[a];
+            double hi = (double)(n[a] - 1);
+            q = fmin(fmax(q, 0.0), hi);
+            double fl = floor(q);
+            if (n[a] >= 2 && fl > hi - 1.0) fl = hi - 1.0;
+            i0[a] = (int)fl;
+            ph[a] = q - fl;
+        }
+        double X[3] = {0.0, 0.0, 0.0};
+        if (t < 8) {
+            int dx = t & 1, dy = (t >> 1) & 1, dz = t >> 2;
+            double wt = (dx ? ph[0] : 1.0 - ph[0]) * (dy ? ph[1] : 1.0 - ph[1]) *
+                        (dz ? ph[2] : 1.0 - ph[2]);
+            if (wt != 0.0) {
+                size_t v = (size_t)(i0[0] + dx) + (size_t)g.nx * ((size_t)(i0[1] + dy) + (size_t)g.ny * (i0[2] + dz));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    double x = widen<double>(mean[a * N + v]);
+                    for (int k = 0; k < K; ++k) x += w.v[k] * widen<double>(U[(size_t)(k * 3 + a) * N + v]);
+                    X[a] = wt * x;
+                }
+            }
+        }
+        // fixed-order sum over the 8 corners
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1) X[a] += __shfl_down(X[a], off, 8);
+            X[a] = __shfl(X[a], 0, 64);
+        }
+        double d2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double pn = pref[a] - X[a];
+            d2 += (pn - p[a]) * (pn - p[a]);
+            p[a] = pn;
+        }
+        if (sqrt(d2) < tol) {
+            conv = 1;
+            break;
+        }
+    }
+    if (t == 0) {
+        out[0] = p[0];
+        out[1] = p[1];
+        out[2] = p[2];
+        out[3] = (double)(it > max_iter ? max_iter : it);
+        out[4] = (double)conv;
+    }
+}
+
+// ============================================================ launchers ===
+static VoxGrid vox(const pcr_grid& g)
+{
+    VoxGrid v;
+    v.nx = g.n[0];
+    v.ny = g.n[1];
+    v.nz = g.n[2];
+    for (int a = 0; a < 3; ++a) v.sp[a] = g.spacing_mm[a];
+    return v;
+}
+static dim3 vox_grid(const pcr_grid& g)
+{
+    return dim3((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]);
+}
+static Chan<double, 8> wvec(const double* w, int K)
+{
+    Chan<double, 8> c;
+    for (int k = 0; k < 8; ++k) c.v[k] = k < K ? w[k] : 0.0;
+    return c;
+}
+
+PadLayout make_pad(const pcr_grid& g, int C)
+{
+    PadLayout L;
+    L.nx = g.n[0];
+    L.ny = g.n[1];
+    L.nz = g.n[2];
+    L.px = L.nx + 3;
+    L.py = L.ny + 3;
+    L.pz = L.nz + 3;
+    L.C = C;
+    return L;
+}
+
+RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G)
+{
+    RayGeom r;
+    double st = std::sin(G.angle_rad), ct = std::cos(G.angle_rad);
+    double s[3] = {G.iso_mm[0] + G.sad_mm * st, G.iso_mm[1] - G.sad_mm * ct, G.iso_mm[2]};
+    double dd = G.sdd_mm - G.sad_mm;
+    double c[3] = {G.iso_mm[0] - dd * st, G.iso_mm[1] + dd * ct, G.iso_mm[2]};
+    double eu[3] = {ct, st, 0.0}, ev[3] = {0.0, 0.0, 1.0};
+    for (int a = 0; a < 3; ++a) {
+        r.sp[a] = g.spacing_mm[a];
+        r.qs[a] = (s[a] - g.origin_mm[a]) / g.spacing_mm[a];
+        r.qc[a] = (c[a] - g.origin_mm[a]) / g.spacing_mm[a];
+        r.eu[a] = eu[a] / g.spacing_mm[a];
+        r.ev[a] = ev[a] / g.spacing_mm[a];
+        r.lim[a] = (double)g.n[a];
+    }
+    r.u0 = -0.5 * (G.nu - 1) * G.du_mm + G.off_u_mm;
+    r.v0 = -0.5 * (G.nv - 1) * G.dv_mm + G.off_v_mm;
+    r.du = G.du_mm;
+    r.dv = G.dv_mm;
+    r.dt = G.step_mm;
+    r.nu = G.nu;
+    r.nv = G.nv;
+    return r;
+}
+
+MarchShape choose_march_shape(const RayGeom& rg)
+{
+    MarchShape ms;
+    ms.tile_u = 16;
+    long rays = (long)rg.nu * rg.nv;
+    // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays when they are few
+    ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
+    return ms;
+}
+
+static int tiles_u_of(const RayGeom& rg, const MarchShape& ms)
+{
+    return (rg.nu + ms.tile_u - 1) / ms.tile_u;
+}
+
+int march_blocks(const RayGeom& rg, const MarchShape& ms)
+{
+    int rpb = 256 / ms.seg, rows = rpb / ms.tile_u;
+    return tiles_u_of(rg, ms) * ((rg.nv + rows - 1) / rows);
+}
+
+int contract_blocks(const pcr_grid& g)
+{
+    dim3 d = vox_grid(g);
+    return (int)(d.x * d.y * d.z);
+}
+
+#define PCR_DISPATCH_S(dt, S, ...)                                   \
+    switch (dt) {                                                    \
+    case PCR_F32: { using S = float; __VA_ARGS__; } break;           \
+    case PCR_F64: { using S = double; __VA_ARGS__; } break;          \
+    case PCR_BF16: { using S = bf16; __VA_ARGS__; } break;           \
+    case PCR_F16: { using S = _Float16; __VA_ARGS__; } break;        \
+    default: return hipErrorInvalidValue;                            \
+    }
+#define PCR_DISPATCH_R(dt, R, ...)                                   \
+    switch (dt) {                                                    \
+    case PCR_F32: { using R = float; __VA_ARGS__; } break;           \
+    case PCR_F64: { using R = double; __VA_ARGS__; } break;          \
+    default: return hipErrorInvalidValue;                            \
+    }
+
+hipError_t launch_compose(pcr_dtype compute, pcr_dtype storage, const pcr_grid& g, int K,
+                          const void* mean, const void* U, const double* w_eff, void* dvf,
+                          hipStream_t s)
+{
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    unsigned blocks = (unsigned)((N + 255) / 256);
+    PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S,
+        k_compose<R, S><<<blocks, 256, 0, s>>>((const S*)mean, (const S*)U, K, N, wvec(w_eff, K),
+                                               (R*)dvf)));
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_plain(pcr_dtype compute, pcr_dtype f0_dtype, const pcr_grid& g,
+                             const void* f0, const void* dvf, void* f, hipStream_t s)
+{
+    PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(f0_dtype, S,
+        k_warp_plain<R, S><<<vox_grid(g), dim3(64, 4), 0, s>>>((const S*)f0, (const R*)dvf, vox(g),
+                                                               (R*)f)));
+    return hipGetLastError();
+}
+
+template <typename R, typename S, typename F>
+static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, bool tangent,
+                               const void* f0, const void* mean, const void* U,
+                               const double* w_eff, void* padded, hipStream_t s)
+{
+    dim3 grid = vox_grid(g), blk(64, 4);
+    auto w = wvec(w_eff, K);
+#define PCR_WF(C, T)                                                                          \
+    k_warp_fused<R, S, F, C, T><<<grid, blk, 0, s>>>((const F*)f0, (const S*)mean, (const S*)U, \
+                                                     K, w, vox(g), L.px, L.py,                \
+                                                     (Chan<R, C>*)padded)
+    if (!tangent) {
+        switch (L.C) {
+        case 1: PCR_WF(1, false); break;
+        case 2: PCR_WF(2, false); break;
+        case 4: PCR_WF(4, false); break;
+        case 8: PCR_WF(8, false); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (L.C) {
+        case 2: PCR_WF(2, true); break;
+        case 4: PCR_WF(4, true); break;
+        case 8: PCR_WF(8, true); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef PCR_WF
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_fused(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
+                             const pcr_grid& g, const PadLayout& L, int K, bool tangent,
+                             const void* f0, const void* mean, const void* U,
+                             const double* w_eff, void* padded, hipStream_t s)
+{
+    PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S, PCR_DISPATCH_S(f0_dtype, F,
+        return warp_fused_c<R, S, F>(g, L, K, tangent, f0, mean, U, w_eff, padded, s))));
+    return hipSuccess;
+}
+
+hipError_t launch_pad(pcr_dtype compute, const PadLayout& L, const void* vol, void* padded,
+                      hipStream_t s)
+{
+    pcr_grid g{};
+    g.n[0] = L.nx; g.n[1] = L.ny; g.n[2] = L.nz;
+    g.spacing_mm[0] = g.spacing_mm[1] = g.spacing_mm[2] = 1.0;
+    PCR_DISPATCH_R(compute, R,
+        k_pad<R><<<vox_grid(g), dim3(64, 4), 0, s>>>((const R*)vol, vox(g), L.px, L.py, (R*)padded));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padded, void* vol,
+                        hipStream_t s)
+{
+    pcr_grid g{};
+    g.n[0] = L.nx; g.n[1] = L.ny; g.n[2] = L.nz;
+    g.spacing_mm[0] = g.spacing_mm[1] = g.spacing_mm[2] = 1.0;
+    PCR_DISPATCH_R(compute, R,
+        k_unpad<R><<<vox_grid(g), dim3(64, 4), 0, s>>>((const R*)padded, vox(g), L.px, L.py, (R*)vol));
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    // A fill kernel rather than a memset node, so that the call is safe to
+    // capture into a graph.  Buffers are whole 4-byte words.
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0 || (uintptr_t)p % 4 != 0) return hipErrorInvalidValue;
+    if ((uintptr_t)p % 16 == 0 && bytes % 16 == 0) {
+        size_t n16 = bytes / 16;
+        unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 8192);
+        k_zero16<<<blocks, 256, 0, s>>>((uint4*)p, n16);
+    } else {
+        size_t n4 = bytes / 4;
+        unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 8192);
+        k_zero4<<<blocks, 256, 0, s>>>((uint32_t*)p, n4);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
+                          const void* padded, const void* y, void* p_out, double* partials,
+                          hipStream_t s)
+{
+    int tiles_u = tiles_u_of(rg, ms);
+    int blocks = march_blocks(rg, ms);
+#define PCR_MARCH(C)                                                                     \
+    k_march<R, C><<<blocks, 256, 0, s>>>(rg, ms, tiles_u, (const Chan<R, C>*)padded, L.px, \
+                                         L.py, (float)L.nx, (float)L.ny, (float)L.nz, kc,  \
+                                         (const R*)y, (R*)p_out, partials)
+    switch (L.C) {
+    case 1: PCR_MARCH(1); break;
+    case 2: PCR_MARCH(2); break;
+    case 4: PCR_MARCH(4); break;
+    case 8: PCR_MARCH(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef PCR_MARCH
+    return hipGetLastError();
+}
+
+hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
+                        const MarchShape& ms, const void* padded, const void* y, void* p_out,
+                        double* partials, hipStream_t s)
+{
+    PCR_DISPATCH_R(compute, R, return march_r<R>(L, kc, rg, ms, padded, y, p_out, partials, s));
+    return hipSuccess;
+}
+
+hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
+                         hipStream_t s)
+{
+    k_reduce<<<1, 256, 0, s>>>(partials, nblocks, stride, nm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(pcr_dtype compute, const PadLayout& L, const RayGeom& rg,
+                              const MarchShape& ms, const void* resid, const void* p,
+                              const void* y, double a, double b, double scale, void* accum,
+                              hipStream_t s)
+{
+    int tiles_u = tiles_u_of(rg, ms);
+    int blocks = march_blocks(rg, ms);
+    PCR_DISPATCH_R(compute, R,
+        k_backproject<R><<<blocks, 256, 0, s>>>(rg, ms, tiles_u, (R*)accum, L.px, L.py,
+                                                (float)L.nx, (float)L.ny, (float)L.nz,
+                                                (const R*)resid, (const R*)p, (const R*)y, a, b,
+                                                scale));
+    return hipGetLastError();
+}
+
+hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
+                           const pcr_grid& g, const PadLayout& L, int K, const void* f0,
+                           const void* mean, const void* U, const double* w_eff,
+                           const void* gpad, double* partials, hipStream_t s)
+{
+    auto w = wvec(w_eff, K);
+    PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S, PCR_DISPATCH_S(f0_dtype, F,
+        k_contract<R, S, F><<<vox_grid(g), dim3(64, 4), 0, s>>>((const F*)f0, (const S*)mean,
+                                                                (const S*)U, K, w, vox(g), L.px,
+                                                                L.py, (const R*)gpad, partials))));
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_adjoint(pcr_dtype compute, const pcr_grid& g, const void* dvf,
+                               const void* gv, void* out, hipStream_t s)
+{
+    PCR_DISPATCH_R(compute, R,
+        k_warp_adjoint<R><<<vox_grid(g), dim3(64, 4), 0, s>>>((const R*)dvf, (const R*)gv, vox(g),
+                                                              (R*)out));
+    return hipGetLastError();
+}
+
+hipError_t launch_localize(pcr_dtype storage, const pcr_grid& g, int K, const void* mean,
+                           const void* U, const double* w_eff, const double* p_ref, double tol,
+                           int max_iter, double* out, hipStream_t s)
+{
+    auto w = wvec(w_eff, K);
+    PCR_DISPATCH_S(storage, S,
+        k_localize<S><<<1, 64, 0, s>>>((const S*)mean, (const S*)U, K, w, vox(g), p_ref[0],
+                                       p_ref[1], p_ref[2], g.origin_mm[0], g.origin_mm[1],
+                                       g.origin_mm[2], tol, max_iter, out));
+    return hipGetLastError();
+}
+
+}  // namespace pcr

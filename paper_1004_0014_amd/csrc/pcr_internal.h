@@ -1,0 +1,107 @@
+// Internal interfaces between the C ABI (api.hip) and the kernels
+// (kernels.hip).  Not installed; the public surface is include/pcr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pcr.h"
+
+namespace pcr {
+
+// Zero-padded multi-channel image layout used by the ray march: voxel (i,j,k)
+// of an nx x ny x nz grid lives at padded cell (i+1, j+1, k+1) of a
+// (nx+3) x (ny+3) x (nz+3) array whose border cells stay zero, channels
+// interleaved per cell.  Sample points are clamped to the support [-1, n] of
+// the interpolant per axis, so every tap of every sample is in bounds and
+// samples outside the support read only zero cells.
+struct PadLayout {
+    int nx, ny, nz;
+    int px, py, pz;      // nx+3, ny+3, nz+3
+    int C;               // channel stride (1, 2, 4 or 8)
+    size_t cells() const { return (size_t)px * py * pz; }
+};
+PadLayout make_pad(const pcr_grid& g, int C);
+
+// Per-projection ray geometry in index space, computed on the host in FP64.
+// A ray from the source q_s towards pixel (iu, iv) has the index-space point
+// q(t) = q_s + t * dq at distance t (mm) from the source.
+struct RayGeom {
+    double qs[3];        // source (index coordinates)
+    double qc[3];        // detector centre (index coordinates)
+    double eu[3], ev[3]; // detector axes (index units per mm)
+    double sp[3];        // voxel spacing (mm)
+    double lim[3];       // upper support bound n_a (the lower one is -1)
+    double u0, v0;       // detector coordinate (mm) of pixel 0 along e_u, e_v
+    double du, dv;       // pixel pitch (mm)
+    double dt;           // sample spacing (mm)
+    int nu, nv;
+};
+RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G);
+
+// Launch shape of the ray-march kernels.
+struct MarchShape {
+    int tile_u;          // pixels along u covered by one wave (64 / tile_u rows)
+    int seg;             // ray segments (threads) per ray: 1, 2 or 4
+};
+MarchShape choose_march_shape(const RayGeom& rg);
+
+// Moments returned by a ray march over channels (f, h_1..h_K):
+//   0 sum y, 1 sum y^2, 2 sum p, 3 sum y p, 4 sum p^2,
+//   5+3k sum p t_k, 6+3k sum y t_k, 7+3k sum t_k,
+// with p = P f and t_k = P h_k per ray.  FP64.
+inline int n_moments(int kc) { return 5 + 3 * (kc - 1); }
+constexpr int kMaxMoments = 5 + 3 * 8;
+
+int march_blocks(const RayGeom& rg, const MarchShape& ms);
+
+// All launchers enqueue on `s` and return hipGetLastError().
+// `compute` is PCR_F32 or PCR_F64 throughout.
+hipError_t launch_compose(pcr_dtype compute, pcr_dtype storage, const pcr_grid& g, int K,
+                          const void* mean, const void* U, const double* w_eff, void* dvf,
+                          hipStream_t s);
+hipError_t launch_warp_plain(pcr_dtype compute, pcr_dtype f0_dtype, const pcr_grid& g,
+                             const void* f0, const void* dvf, void* f, hipStream_t s);
+// Fused compose + warp (+ tangents): writes channel 0 = f and, when
+// tangent, channels 1..K = h_k = (df/dx) . u_k into the padded layout.
+hipError_t launch_warp_fused(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
+                             const pcr_grid& g, const PadLayout& L, int K, bool tangent,
+                             const void* f0, const void* mean, const void* U,
+                             const double* w_eff, void* padded, hipStream_t s);
+hipError_t launch_pad(pcr_dtype compute, const PadLayout& L, const void* vol, void* padded,
+                      hipStream_t s);
+hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padded, void* vol,
+                        hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Ray march over kc used channels of a padded image; writes p (may be null)
+// and per-block moment partials (may be null; y required then).
+hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
+                        const MarchShape& ms, const void* padded, const void* y, void* p_out,
+                        double* partials, hipStream_t s);
+// Fixed-order final sum of per-block partials: out[m] for m < nm.
+hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
+                         hipStream_t s);
+// Scatter of the residual: accum (padded, 1 channel, pre-zeroed) +=
+// P^T r with r = resid (when resid != null) else scale * (p - a y - b).
+hipError_t launch_backproject(pcr_dtype compute, const PadLayout& L, const RayGeom& rg,
+                              const MarchShape& ms, const void* resid, const void* p,
+                              const void* y, double a, double b, double scale, void* accum,
+                              hipStream_t s);
+// Gradient contraction: partials[block][k] = sum_v g[v] (df/dx)[v] . u_k[v],
+// g read from the padded accumulator.
+int contract_blocks(const pcr_grid& g);
+hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
+                           const pcr_grid& g, const PadLayout& L, int K, const void* f0,
+                           const void* mean, const void* U, const double* w_eff,
+                           const void* gpad, double* partials, hipStream_t s);
+hipError_t launch_warp_adjoint(pcr_dtype compute, const pcr_grid& g, const void* dvf,
+                               const void* gv, void* out, hipStream_t s);
+// Fixed-point localisation; writes out[0..2] = p, out[3] = iterations,
+// out[4] = converged (1) or not (0).
+hipError_t launch_localize(pcr_dtype storage, const pcr_grid& g, int K, const void* mean,
+                           const void* U, const double* w_eff, const double* p_ref, double tol,
+                           int max_iter, double* out, hipStream_t s);
+
+}  // namespace pcr
