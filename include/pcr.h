@@ -167,6 +167,16 @@ pcr_status pcr_warp_volume(const pcr_grid* grid, pcr_dtype f0_dtype, const void*
 pcr_status pcr_warp_adjoint(const pcr_grid* grid, pcr_dtype compute, const void* dvf_dev,
                             const void* g_dev, void* out_dev, void* stream);
 
+/* Gradient contraction (section 2.2: the U^T (df/dx)^T factors of the
+ * gradient): grad_host[k] = scale_k * sum_v g[v] sum_a (df/dx_a)[v] U_k[a][v],
+ * where df/dx is the exact derivative of the trilinear warp of f0 at the
+ * displaced point of voxel v for the DVF mean + U (scale * w).  g_dev [N] of
+ * dtype `compute`; f0_dev of dtype f0_dtype; FP64 accumulation in a fixed
+ * order (bitwise reproducible).  Synchronises `stream`. */
+pcr_status pcr_warp_contract(const pcr_grid* grid, const pcr_model* model, pcr_dtype f0_dtype,
+                             const void* f0_dev, const double* w_host, pcr_dtype compute,
+                             const void* g_dev, double* grad_host, void* stream);
+
 /* Forward projection P vol (eq. (2)'s projection matrix, discretised as in
  * the conventions above).  vol_dev [N] and proj_dev [nv][nu] of dtype
  * `compute` (F32 or F64); proj_dev is overwritten.  Allocates a padded
@@ -177,8 +187,9 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom,
 
 /* Backprojection P^T resid, the exact transpose of pcr_forward_project (the
  * P^T of the gradient formula in section 2.2; no factor 2).  resid_dev
- * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  Uses
- * floating-point atomics (order-dependent last bits). */
+ * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  Each
+ * workgroup accumulates one brick of the output in LDS with LDS atomics
+ * (order-dependent last bits; no global atomics). */
 pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom,
                                     pcr_dtype compute, const void* resid_dev,
                                     void* vol_dev, void* stream);
@@ -226,6 +237,15 @@ pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model,
                               const double* w_host, const double p_ref_mm[3], double tol_mm,
                               int32_t max_iter, double p_out_mm[3], int32_t* iters,
                               void* stream);
+
+/* Opt-in kernel timing (tracing).  While enabled, every kernel the library
+ * launches is bracketed by two HIP events on the stream it runs on.  Enabling
+ * resets the totals.  pcr_profile_read resolves pending events (waiting for
+ * them), fills up to `max` entries of names (static strings), total_ms and
+ * counts (any may be NULL) and returns the number of kernel kinds.  Global to
+ * the process; thread-safe. */
+void pcr_profile_enable(int32_t on);
+int32_t pcr_profile_read(int32_t max, const char** names, double* total_ms, int64_t* counts);
 
 #ifdef __cplusplus
 }

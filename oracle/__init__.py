@@ -69,6 +69,7 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
         G, Gm = C.POINTER(_Grid), C.POINTER(_Geom)
         sig = {
+            "orc_num_threads": (C.c_int, []),
             "orc_interp": (C.c_double, [_PD, C.POINTER(C.c_int), _PD]),
             "orc_interp_grad": (None, [_PD, C.POINTER(C.c_int), _PD, _PD]),
             "orc_compose": (None, [G, C.c_int, _PD, _PD, _PD, _PD]),
@@ -130,6 +131,10 @@ def _n(grid):
 
 
 # ------------------------------------------------------------ wrappers -----
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
 def interp(F, grid, q):
     F = _arr(F)
     q = _arr(q)

@@ -19,6 +19,16 @@
 #define ORC_ENOCONV (-4)
 #define ORC_EDIVERGE (-5)
 
+/* Threads the OpenMP regions of the oracle use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static long vol_size(const orc_grid* g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
 
 static double fetch(const double* F, const int n[3], long i, long j, long k)

@@ -54,6 +54,8 @@ typedef struct {
     double J0, J, gnorm0, gnorm, a, b;
 } orc_stats;
 
+int orc_num_threads(void);
+
 /* Trilinear interpolant T[F](q) at index-space point q; F = 0 outside. */
 double orc_interp(const double* F, const int n[3], const double q[3]);
 /* Exact partial derivatives dT/dq_a of the same interpolant (floor cell). */

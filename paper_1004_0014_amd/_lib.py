@@ -95,6 +95,10 @@ def lib():
                                                             _PD, C.POINTER(SolveStats), _P]),
             "pcr_localize_tumor": (C.c_int32, [G, Md, _PD, _PD, C.c_double, C.c_int32, _PD,
                                                C.POINTER(C.c_int32), _P]),
+            "pcr_warp_contract": (C.c_int32, [G, Md, C.c_int, _P, _PD, C.c_int, _P, _PD, _P]),
+            "pcr_profile_enable": (None, [C.c_int32]),
+            "pcr_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_char_p), _PD,
+                                             C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -220,6 +224,15 @@ def backproject_residual(grid, geom, resid: torch.Tensor, out=None, stream=None)
     return out
 
 
+def warp_contract(grid, model: DeviceModel, f0: torch.Tensor, w, gvol: torch.Tensor, stream=None):
+    """[K] list: scale_k sum_v g[v] (df/dx)[v] . U_k[v] at the DVF for w."""
+    g = make_grid(grid)
+    out = (C.c_double * model.K)()
+    _check(lib().pcr_warp_contract(C.byref(g), C.byref(model.struct), _dtype(f0), _ptr(f0), _dd(w),
+                                   _dtype(gvol), _ptr(gvol), out, _stream(stream)))
+    return [out[k] for k in range(model.K)]
+
+
 def localize_tumor(grid, model: DeviceModel, w, p_ref, tol=1e-6, max_iter=200, stream=None):
     """Returns (position mm [3], status, iterations)."""
     g = make_grid(grid)
@@ -290,3 +303,18 @@ class Context:
                                                      C.byref(st), _stream(stream)),
                ok=(PCR_OK, PCR_ENOCONV))
         return [w[k] for k in range(self.K)], (ab[0], ab[1]), st.as_dict()
+
+
+def profile_enable(on: bool = True):
+    """Per-kernel HIP-event timing inside the library (resets when enabled)."""
+    lib().pcr_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel: (total_ms, launches)} for kernels launched while enabled."""
+    n = 32
+    names = (C.c_char_p * n)()
+    tot = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    k = lib().pcr_profile_read(n, names, tot, cnt)
+    return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(k, n)) if cnt[i] > 0}

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -203,8 +204,116 @@ static pcr_status current_device(int* dev)
     return PCR_OK;
 }
 
+// ----------------------------------------------------------- profiler ----
+// Opt-in per-kernel timing: every launch of the library is bracketed by two
+// HIP events on the stream it runs on; durations are resolved when read.
+namespace prof {
+enum Id { WARP, MARCH, REDUCE, BACKPROJ, CONTRACT, LOCALIZE, ZERO, PAD, UNPAD, COMPOSE, WARP_PLAIN,
+          WARP_ADJ, NKERN };
+static const char* kNames[NKERN] = {"warp_fused", "march", "reduce", "backproject", "contract",
+                                    "localize", "zero", "pad", "unpad", "compose", "warp",
+                                    "warp_adjoint"};
+struct Rec {
+    hipEvent_t a, b;
+    int id;
+};
+static std::mutex mu;
+static bool enabled = false;
+static std::vector<Rec> pending;
+static std::vector<hipEvent_t> pool;
+static double total_ms[NKERN];
+static long long counts[NKERN];
+static long long dropped = 0;
+
+static hipEvent_t get_event()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Scope {
+    hipStream_t s;
+    int id;
+    hipEvent_t a = nullptr;
+    Scope(int id_, hipStream_t s_) : s(s_), id(id_)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!enabled) return;
+        a = get_event();
+        if (a && hipEventRecord(a, s) != hipSuccess) {
+            pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~Scope()
+    {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(mu);
+        hipEvent_t b = get_event();
+        if (!b || hipEventRecord(b, s) != hipSuccess) {
+            pool.push_back(a);
+            if (b) pool.push_back(b);
+            ++dropped;
+            return;
+        }
+        pending.push_back({a, b, id});
+    }
+};
+
+static void flush_locked()
+{
+    for (auto& r : pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            total_ms[r.id] += ms;
+            counts[r.id] += 1;
+        } else {
+            ++dropped;
+        }
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+}
+}  // namespace prof
+
+#define PROF(id, s) prof::Scope prof_scope_##__LINE__(prof::id, s)
+
 // ============================================================ C ABI =======
 extern "C" {
+
+void pcr_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::flush_locked();
+    if (on) {
+        for (int i = 0; i < prof::NKERN; ++i) {
+            prof::total_ms[i] = 0.0;
+            prof::counts[i] = 0;
+        }
+        prof::dropped = 0;
+    }
+    prof::enabled = on != 0;
+}
+
+int32_t pcr_profile_read(int32_t max, const char** names, double* total_ms, int64_t* counts)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::flush_locked();
+    int n = std::min<int>(max, prof::NKERN);
+    for (int i = 0; i < n; ++i) {
+        if (names) names[i] = prof::kNames[i];
+        if (total_ms) total_ms[i] = prof::total_ms[i];
+        if (counts) counts[i] = prof::counts[i];
+    }
+    return prof::NKERN;
+}
 
 const char* pcr_version(void) { return PCR_VERSION_STRING; }
 const char* pcr_last_error(void) { return g_err.c_str(); }
@@ -236,8 +345,12 @@ pcr_status pcr_dvf_compose(const pcr_grid* grid, const pcr_model* model, const d
     if (!dvf_dev) return fail(PCR_EINVAL, "dvf_dev is NULL");
     double w_eff[8];
     effective_w(*model, w_host, w_eff);
-    HIP_TRY(launch_compose(compute, model->storage, *grid, model->K, model->mean, model->U, w_eff,
-                           dvf_dev, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        PROF(COMPOSE, s);
+        HIP_TRY(launch_compose(compute, model->storage, *grid, model->K, model->mean, model->U, w_eff,
+                               dvf_dev, s));
+    }
     return PCR_OK;
 }
 
@@ -249,7 +362,11 @@ pcr_status pcr_warp_volume(const pcr_grid* grid, pcr_dtype f0_dtype, const void*
     PCR_TRY(check_compute(compute));
     if (!f0_dev || !dvf_dev || !f_dev) return fail(PCR_EINVAL, "NULL device pointer");
     if (f_dev == f0_dev) return fail(PCR_EINVAL, "f_dev must not alias f0_dev");
-    HIP_TRY(launch_warp_plain(compute, f0_dtype, *grid, f0_dev, dvf_dev, f_dev, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        PROF(WARP_PLAIN, s);
+        HIP_TRY(launch_warp_plain(compute, f0_dtype, *grid, f0_dev, dvf_dev, f_dev, s));
+    }
     return PCR_OK;
 }
 
@@ -261,8 +378,14 @@ pcr_status pcr_warp_adjoint(const pcr_grid* grid, pcr_dtype compute, const void*
     if (!dvf_dev || !g_dev || !out_dev) return fail(PCR_EINVAL, "NULL device pointer");
     size_t N = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_zero(out_dev, N * dtype_size(compute), s));
-    HIP_TRY(launch_warp_adjoint(compute, *grid, dvf_dev, g_dev, out_dev, s));
+    {
+        PROF(ZERO, s);
+        HIP_TRY(launch_zero(out_dev, N * dtype_size(compute), s));
+    }
+    {
+        PROF(WARP_ADJ, s);
+        HIP_TRY(launch_warp_adjoint(compute, *grid, dvf_dev, g_dev, out_dev, s));
+    }
     return PCR_OK;
 }
 
@@ -279,11 +402,21 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     PadLayout L = make_pad(*grid, 1);
     size_t bytes = L.cells() * dtype_size(compute);
     PCR_TRY(tls.pad.ensure(bytes, dev, s));
-    HIP_TRY(launch_zero(tls.pad.p, bytes, s));
-    HIP_TRY(launch_pad(compute, L, vol_dev, tls.pad.p, s));
+    {
+        PROF(ZERO, s);
+        HIP_TRY(launch_zero(tls.pad.p, bytes, s));
+    }
+    {
+        PROF(PAD, s);
+        HIP_TRY(launch_pad(compute, L, vol_dev, tls.pad.p, s));
+    }
     RayGeom rg = make_ray_geom(*grid, *geom);
     MarchShape ms = choose_march_shape(rg);
-    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, s));
+    {
+        PROF(MARCH, s);
+        HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr,
+                             nullptr, s));
+    }
     return PCR_OK;
 }
 
@@ -295,17 +428,47 @@ pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom, 
     PCR_TRY(check_compute(compute));
     if (!resid_dev || !vol_dev) return fail(PCR_EINVAL, "NULL device pointer");
     hipStream_t s = (hipStream_t)stream;
+    RayGeom rg = make_ray_geom(*grid, *geom);
+    {
+        PROF(BACKPROJ, s);
+        HIP_TRY(launch_backproject(compute, *grid, rg, resid_dev, nullptr, nullptr, 0.0, 0.0, 1.0,
+                                   vol_dev, s));
+    }
+    return PCR_OK;
+}
+
+pcr_status pcr_warp_contract(const pcr_grid* grid, const pcr_model* model, pcr_dtype f0_dtype,
+                             const void* f0_dev, const double* w_host, pcr_dtype compute,
+                             const void* g_dev, double* grad_host, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_model(model));
+    PCR_TRY(check_storage(f0_dtype));
+    PCR_TRY(check_compute(compute));
+    PCR_TRY(check_finite(w_host, model->K, "w"));
+    if (!f0_dev || !g_dev || !grad_host) return fail(PCR_EINVAL, "NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
     int dev;
     PCR_TRY(current_device(&dev));
-    PadLayout L = make_pad(*grid, 1);
-    size_t bytes = L.cells() * dtype_size(compute);
-    PCR_TRY(tls.pad.ensure(bytes, dev, s));
-    HIP_TRY(launch_zero(tls.pad.p, bytes, s));
-    RayGeom rg = make_ray_geom(*grid, *geom);
-    MarchShape ms = choose_march_shape(rg);
-    HIP_TRY(launch_backproject(compute, L, rg, ms, resid_dev, nullptr, nullptr, 0.0, 0.0, 1.0,
-                               tls.pad.p, s));
-    HIP_TRY(launch_unpad(compute, L, tls.pad.p, vol_dev, s));
+    const int nb = contract_blocks(*grid);
+    PCR_TRY(tls.pad.ensure((size_t)nb * 8 * sizeof(double) + 8 * sizeof(double), dev, s));
+    PCR_TRY(tls.host.ensure(8));
+    double w_eff[8];
+    effective_w(*model, w_host, w_eff);
+    double* part = (double*)tls.pad.p;
+    double* out = part + (size_t)nb * 8;
+    {
+        PROF(CONTRACT, s);
+        HIP_TRY(launch_contract(compute, model->storage, f0_dtype, *grid, model->K, f0_dev, model->mean,
+                                model->U, w_eff, g_dev, part, s));
+    }
+    {
+        PROF(REDUCE, s);
+        HIP_TRY(launch_reduce(part, nb, 8, model->K, out, s));
+    }
+    HIP_TRY(hipMemcpyAsync(tls.host.p, out, model->K * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < model->K; ++k) grad_host[k] = tls.host.p[k] * (model->scale ? model->scale[k] : 1.0);
     return PCR_OK;
 }
 
@@ -326,8 +489,11 @@ pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model, cons
     PCR_TRY(tls.host.ensure(8));
     double w_eff[8];
     effective_w(*model, w_host, w_eff);
-    HIP_TRY(launch_localize(model->storage, *grid, model->K, model->mean, model->U, w_eff, p_ref_mm,
-                            tol_mm, max_iter, (double*)tls.small.p, s));
+    {
+        PROF(LOCALIZE, s);
+        HIP_TRY(launch_localize(model->storage, *grid, model->K, model->mean, model->U, w_eff, p_ref_mm,
+                                tol_mm, max_iter, (double*)tls.small.p, s));
+    }
     HIP_TRY(hipMemcpyAsync(tls.host.p, tls.small.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int a = 0; a < 3; ++a) p_out_mm[a] = tls.host.p[a];
@@ -347,10 +513,12 @@ struct pcr_ctx {
     const void* f0;
     int device;
     PadLayout Lc, L1;     // fused (K+1 channels) and single-channel layouts
-    DevBuf volc, vol1, acc1, p, partials, moments;
+    int volc_yfast = -1;  // layout currently held by volc (-1: not zeroed for any)
+    DevBuf volc, vol1, acc1, p, partials, moments, counter;
     HostBuf host;
     ~pcr_ctx()
     {
+        counter.release();
         volc.release();
         vol1.release();
         acc1.release();
@@ -409,10 +577,11 @@ struct Moments {
 struct Solver {
     pcr_ctx* c;
     hipStream_t s;
-    RayGeom rg;
-    MarchShape ms;
+    RayGeom rg;      // x-fastest geometry (adjoint path)
+    RayGeom rgc;     // geometry in the fused image's layout
+    MarchShape ms, msc;
     int M;
-    int blocks;
+    int blocks, blocksc;
     const void* y;
 
     pcr_status prepare(const void* y_, const pcr_geom& G, int mode)
@@ -422,8 +591,22 @@ struct Solver {
         ms = choose_march_shape(rg);
         M = G.nu * G.nv;
         blocks = march_blocks(rg, ms);
+        const bool yfast = prefer_yfast(G);
+        c->Lc = make_pad(c->grid, c->Lc.C, yfast);
+        rgc = make_ray_geom(c->grid, G, yfast);
+        msc = choose_march_shape(rgc);
+        blocksc = march_blocks(rgc, msc);
+        if (mode == PCR_GRAD_FUSED && c->volc_yfast != (int)yfast) {
+            // border cells of one layout are interior cells of the other
+            {
+                PROF(ZERO, s);
+                HIP_TRY(launch_zero(c->volc.p, c->volc.bytes, s));
+            }
+            c->volc_yfast = (int)yfast;
+        }
         int cblocks = contract_blocks(c->grid);
-        PCR_TRY(c->partials.ensure((size_t)std::max(blocks, cblocks) * kMaxMoments * sizeof(double),
+        PCR_TRY(c->partials.ensure((size_t)std::max(std::max(blocks, blocksc), cblocks) * kMaxMoments *
+                                       sizeof(double),
                                    c->device, s));
         PCR_TRY(c->moments.ensure(kMaxMoments * sizeof(double), c->device, s));
         PCR_TRY(c->host.ensure(kMaxMoments));
@@ -433,7 +616,8 @@ struct Solver {
             bool fresh = c->vol1.p == nullptr;
             PCR_TRY(c->vol1.ensure(b1, c->device, s));
             if (fresh) HIP_TRY(launch_zero(c->vol1.p, c->vol1.bytes, s));
-            PCR_TRY(c->acc1.ensure(b1, c->device, s));
+            PCR_TRY(c->acc1.ensure((size_t)c->grid.n[0] * c->grid.n[1] * c->grid.n[2] * esz,
+                                   c->device, s));
             PCR_TRY(c->p.ensure((size_t)M * esz, c->device, s));
         }
         return PCR_OK;
@@ -446,24 +630,35 @@ struct Solver {
         double w_eff[8];
         effective_w(c->model, w, w_eff);
         const int K = c->model.K;
-        int kc, stride;
+        const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
+        double* mom = (double*)c->moments.p;
+        unsigned* ctr = (unsigned*)c->counter.p;
         if (mode == PCR_GRAD_FUSED) {
-            kc = K + 1;
-            stride = 5 + 3 * (c->Lc.C - 1);
-            HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->Lc, K,
-                                      true, c->f0, c->model.mean, c->model.U, w_eff, c->volc.p, s));
-            HIP_TRY(launch_march(c->compute, c->Lc, kc, rg, ms, c->volc.p, y, nullptr,
-                                 (double*)c->partials.p, s));
+            {
+                PROF(WARP, s);
+                HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->Lc,
+                                          K, true, c->f0, c->model.mean, c->model.U, w_eff,
+                                          c->volc.p, s));
+            }
+            {
+                PROF(MARCH, s);
+                HIP_TRY(launch_march(c->compute, c->Lc, kc, rgc, msc, c->volc.p, y, nullptr,
+                                     (double*)c->partials.p, mom, ctr, s));
+            }
         } else {
-            kc = 1;
-            stride = 5;
-            HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1, K,
-                                      false, c->f0, c->model.mean, c->model.U, w_eff, c->vol1.p, s));
-            HIP_TRY(launch_march(c->compute, c->L1, 1, rg, ms, c->vol1.p, y, c->p.p,
-                                 (double*)c->partials.p, s));
+            {
+                PROF(WARP, s);
+                HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1,
+                                          K, false, c->f0, c->model.mean, c->model.U, w_eff,
+                                          c->vol1.p, s));
+            }
+            {
+                PROF(MARCH, s);
+                HIP_TRY(launch_march(c->compute, c->L1, 1, rg, ms, c->vol1.p, y, c->p.p,
+                                     (double*)c->partials.p, mom, ctr, s));
+            }
         }
         int nm = n_moments(kc);
-        HIP_TRY(launch_reduce((const double*)c->partials.p, blocks, stride, nm, (double*)c->moments.p, s));
         HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, nm * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         std::memset(out.m, 0, sizeof out.m);
@@ -480,14 +675,22 @@ struct Solver {
         double w_eff[8];
         effective_w(c->model, w, w_eff);
         const int K = c->model.K;
-        HIP_TRY(launch_zero(c->acc1.p, c->acc1.bytes, s));
-        HIP_TRY(launch_backproject(c->compute, c->L1, rg, ms, nullptr, c->p.p, y, a, b, 2.0,
-                                   c->acc1.p, s));
-        HIP_TRY(launch_contract(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1, K, c->f0,
-                                c->model.mean, c->model.U, w_eff, c->acc1.p,
-                                (double*)c->partials.p, s));
-        HIP_TRY(launch_reduce((const double*)c->partials.p, contract_blocks(c->grid), 8, K,
-                              (double*)c->moments.p, s));
+        {
+            PROF(BACKPROJ, s);
+            HIP_TRY(launch_backproject(c->compute, c->grid, rg, nullptr, c->p.p, y, a, b, 2.0,
+                                       c->acc1.p, s));
+        }
+        {
+            PROF(CONTRACT, s);
+            HIP_TRY(launch_contract(c->compute, c->model.storage, c->f0_dtype, c->grid, K, c->f0,
+                                    c->model.mean, c->model.U, w_eff, c->acc1.p,
+                                    (double*)c->partials.p, s));
+        }
+        {
+            PROF(REDUCE, s);
+            HIP_TRY(launch_reduce((const double*)c->partials.p, contract_blocks(c->grid), 8, K,
+                                  (double*)c->moments.p, s));
+        }
         HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (int k = 0; k < K; ++k) grad[k] = c->host.p[k];
@@ -561,11 +764,18 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
     c->Lc = make_pad(*grid, channels_for(model->K + 1));
     c->L1 = make_pad(*grid, 1);
     size_t esz = compute == PCR_F64 ? 8 : 4;
+    if (compute == PCR_F32 && (double)c->Lc.cells() * c->Lc.C * esz >= 2147483648.0) {
+        delete c;
+        return fail(PCR_EINVAL, "padded multi-channel image exceeds 2 GiB (32-bit offsets)");
+    }
     st = c->volc.ensure(c->Lc.cells() * c->Lc.C * esz, c->device, nullptr);
+    if (st == PCR_OK) st = c->counter.ensure(256, c->device, nullptr);
     if (st == PCR_OK) {
         hipError_t e = launch_zero(c->volc.p, c->volc.bytes, nullptr);
+        if (e == hipSuccess) e = launch_zero(c->counter.p, c->counter.bytes, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) st = fail(PCR_EDEVICE, "zeroing context scratch: %s", hipGetErrorString(e));
+        c->volc_yfast = 0;
     }
     if (st != PCR_OK) {
         delete c;

@@ -21,6 +21,8 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
+#include <utility>
 
 #include "pcr_internal.h"
 
@@ -93,18 +95,19 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
 __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ part, int nblocks,
                                                 int stride, int nm, double* __restrict__ out)
 {
-    __shared__ double buf[256];
-    for (int m = 0; m < nm; ++m) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) s += part[(size_t)b * stride + m];
-        buf[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[m] = buf[0];
-        __syncthreads();
+    // thread (chunk c, moment m): sum of blocks c, c+8, ... then chunks in order
+    __shared__ double chunk[8][32];
+    const int m = threadIdx.x & 31, c = threadIdx.x >> 5;
+    double s = 0.0;
+    if (m < nm)
+        for (int b = c; b < nblocks; b += 8) s += part[(size_t)b * stride + m];
+    chunk[c][m] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < nm) {
+        double t = chunk[0][threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) t += chunk[k][threadIdx.x];
+        out[threadIdx.x] = t;
     }
 }
 
@@ -186,16 +189,14 @@ __global__ void __launch_bounds__(256) k_warp_plain(const S* __restrict__ f0,
     f[v] = sample_f0<R, S, false>(f0, g.nx, g.ny, g.nz, qx, qy, qz, nullptr);
 }
 
-// Fused compose + warp (+ tangents) into the padded multi-channel layout.
+// Fused compose + warp (+ tangents) of one voxel: channel 0 = f, channels
+// 1..K = h_k = sum_a (1/s_a) dT[f0]/dq_a u_k[a] (tangent), rest zero.
 template <typename R, typename S, typename F, int C, bool TAN>
-__global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
-                                                    const S* __restrict__ mean,
-                                                    const S* __restrict__ U, int K,
-                                                    Chan<double, 8> w, VoxGrid g, int px, int py,
-                                                    Chan<R, C>* __restrict__ out)
+__device__ __forceinline__ Chan<R, C> warp_cell(const F* __restrict__ f0, const S* __restrict__ mean,
+                                                const S* __restrict__ U, int K,
+                                                const Chan<double, 8>& w, const VoxGrid& g, int i,
+                                                int j, int k)
 {
-    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
     size_t N = (size_t)g.nx * g.ny * g.nz;
     size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
     R x[3];
@@ -227,8 +228,48 @@ __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
         for (int kk = 0; kk < C - 1; ++kk)
             if (kk < K) o.v[kk + 1] = G0 * u[TAN ? kk : 0][0] + G1 * u[TAN ? kk : 0][1] + G2 * u[TAN ? kk : 0][2];
     }
-    size_t pc = (size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1));
-    out[pc] = o;
+    return o;
+}
+
+// x-fastest padded layout: block 64 (x) x 4 (y), coalesced in x both ways.
+template <typename R, typename S, typename F, int C, bool TAN>
+__global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
+                                                    const S* __restrict__ mean,
+                                                    const S* __restrict__ U, int K,
+                                                    Chan<double, 8> w, VoxGrid g, int px, int py,
+                                                    Chan<R, C>* __restrict__ out)
+{
+    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    Chan<R, C> o = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
+    out[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))] = o;
+}
+
+// y-fastest padded layout: a 32 x 32 (x, y) tile per block, computed with
+// x-contiguous reads, staged in LDS and written as 32-cell runs along y.
+template <typename R, typename S, typename F, int C, bool TAN>
+__global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
+                                                       const S* __restrict__ mean,
+                                                       const S* __restrict__ U, int K,
+                                                       Chan<double, 8> w, VoxGrid g, int px,
+                                                       int py, Chan<R, C>* __restrict__ out)
+{
+    __shared__ Chan<R, C> tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + tx, j = j0 + ty + 8 * r;
+        if (i < g.nx && j < g.ny) tile[ty + 8 * r][tx] = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int jl = tx, il = ty + 8 * r;
+        const int i = i0 + il, j = j0 + jl;
+        if (i < g.nx && j < g.ny)
+            out[(size_t)(j + 1) + (size_t)px * ((size_t)(i + 1) + (size_t)py * (k + 1))] = tile[jl][il];
+    }
 }
 
 template <typename R>
@@ -420,49 +461,327 @@ __global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int til
     }
 }
 
-// Exact transpose of the single-channel march: scatter r * dt * weight.
-template <typename R>
-__global__ void __launch_bounds__(256) k_backproject(RayGeom g, MarchShape ms, int tiles_u,
-                                                     R* __restrict__ acc, int px, int py,
-                                                     float fnx, float fny, float fnz,
-                                                     const R* __restrict__ resid,
-                                                     const R* __restrict__ p,
-                                                     const R* __restrict__ y, double a, double b,
-                                                     double scale)
+// ---------------------------------------------------- FP32 ray march ----
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
+// contiguous run of tiles (a band of detector rows), so that the rays sharing
+// an XCD's L2 cross the same part of the volume.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
 {
-    int iu, iv, sid, rloc;
-    ray_of_thread(ms, tiles_u, iu, iv, sid, rloc);
-    if (iu >= g.nu || iv >= g.nv) return;
-    size_t pix = iu + (size_t)g.nu * iv;
-    R r;
-    if (resid)
-        r = resid[pix];
-    else
-        r = (R)(scale * ((double)p[pix] - a * (double)y[pix] - b));
-    if (r == (R)0) return;
-    const R rw = r * (R)g.dt;
-    RaySeg<R> rs = ray_segment<R>(g, iu, iv, ms.seg, sid);
-    const long pxy = (long)px * py;
-    R* base = acc + (1 + px + pxy);
-    for (int m = 0; m < rs.count; ++m) {
-        R fm = (R)m;
-        R qx = clampv(fma(fm, rs.dq[0], rs.q0[0]), (R)-1, (R)fnx);
-        R qy = clampv(fma(fm, rs.dq[1], rs.q0[1]), (R)-1, (R)fny);
-        R qz = clampv(fma(fm, rs.dq[2], rs.q0[2]), (R)-1, (R)fnz);
-        R flx = floor(qx), fly = floor(qy), flz = floor(qz);
-        int ix = (int)flx, iy = (int)fly, iz = (int)flz;
-        R ax = qx - flx, ay = qy - fly, az = qz - flz;
-        R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
-        R w00 = by * bz * rw, w10 = ay * bz * rw, w01 = by * az * rw, w11 = ay * az * rw;
-        R* c0 = base + ((long)ix + (long)px * iy + pxy * iz);
-        unsafeAtomicAdd(c0, bx * w00);
-        unsafeAtomicAdd(c0 + 1, ax * w00);
-        unsafeAtomicAdd(c0 + px, bx * w10);
-        unsafeAtomicAdd(c0 + px + 1, ax * w10);
-        unsafeAtomicAdd(c0 + pxy, bx * w01);
-        unsafeAtomicAdd(c0 + pxy + 1, ax * w01);
-        unsafeAtomicAdd(c0 + pxy + px, bx * w11);
-        unsafeAtomicAdd(c0 + pxy + px + 1, ax * w11);
+    const int q = nb >> 3, rem = nb & 7, x = b & 7;
+    return x * q + min(x, rem) + (b >> 3);
+}
+
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// One padded cell pair (x and x+1) of C float channels via raw buffer loads
+// at byte offset voff (+ scalar stride soff).
+template <int C>
+struct CellPair {
+    float a[C], b[C];
+};
+// Same pair through plain global loads (base pointer + byte offset).
+template <int C>
+__device__ __forceinline__ CellPair<C> load_pair_g(const char* base, int off)
+{
+    CellPair<C> p;
+    const float* a = (const float*)(base + off);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        p.a[c] = a[c];
+        p.b[c] = a[C + c];
+    }
+    return p;
+}
+
+template <int C>
+__device__ __forceinline__ CellPair<C> load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    CellPair<C> p;
+    if constexpr (C == 1) {
+        v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        p.a[0] = __int_as_float(v.x);
+        p.b[0] = __int_as_float(v.y);
+    } else if constexpr (C == 2) {
+        v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        p.a[0] = __int_as_float(v.x);
+        p.a[1] = __int_as_float(v.y);
+        p.b[0] = __int_as_float(v.z);
+        p.b[1] = __int_as_float(v.w);
+    } else {
+#pragma unroll
+        for (int h = 0; h < C / 4; ++h) {
+            v4i u = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16 * h, soff, 0);
+            v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 4 * C + 16 * h, soff, 0);
+            p.a[4 * h + 0] = __int_as_float(u.x);
+            p.a[4 * h + 1] = __int_as_float(u.y);
+            p.a[4 * h + 2] = __int_as_float(u.z);
+            p.a[4 * h + 3] = __int_as_float(u.w);
+            p.b[4 * h + 0] = __int_as_float(v.x);
+            p.b[4 * h + 1] = __int_as_float(v.y);
+            p.b[4 * h + 2] = __int_as_float(v.z);
+            p.b[4 * h + 3] = __int_as_float(v.w);
+        }
+    }
+    return p;
+}
+
+struct MarchArgs {
+    RayGeom g;
+    MarchShape ms;
+    int tiles_u;
+    const void* vol;       // padded image, C float channels per cell
+    unsigned vol_bytes;
+    int ys, zs;            // byte strides of the padded y and z axes
+    float fn1[3];          // clamp bound n_a + 1 (padded index space)
+    int kc;                // channels used
+    const float* y;        // measured projection (moments) or null
+    float* p_out;          // projection out or null
+    double* partials;      // [blocks][NM] or null
+    double* moments;       // final moments (last block) or null
+    unsigned* counter;     // last-block counter
+};
+
+template <int C, bool BUF>
+__global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
+{
+    const RayGeom& g = A.g;
+    const int rpb = 256 / A.ms.seg;
+    const int rloc = threadIdx.x % rpb, sid = threadIdx.x / rpb;
+    const int rows = rpb / A.ms.tile_u;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tu = tile % A.tiles_u, tv = tile / A.tiles_u;
+    const int iu = tu * A.ms.tile_u + rloc % A.ms.tile_u;
+    const int iv = tv * rows + rloc / A.ms.tile_u;
+    const bool valid = iu < g.nu && iv < g.nv;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    if (valid) {
+        RaySeg<float> rs = ray_segment<float>(g, iu, iv, A.ms.seg, sid);
+        // padded index space: cell i+1 holds voxel i, so q + 1 >= 0 after the
+        // clamp and truncation is the floor
+        const float q0x = rs.q0[0] + 1.f, q0y = rs.q0[1] + 1.f, q0z = rs.q0[2] + 1.f;
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.vol), (short)0, A.vol_bytes, 0x00020000);
+        const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs;
+        for (int m = 0; m < rs.count; ++m) {
+            const float fm = (float)m;
+            float qx = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[0], q0x), 0.f, A.fn1[0]);
+            float qy = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[1], q0y), 0.f, A.fn1[1]);
+            float qz = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[2], q0z), 0.f, A.fn1[2]);
+            const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
+            const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
+                        az = __builtin_amdgcn_fractf(qz);
+            const int voff = ix * (4 * C) + __umul24(iy, YS) + __umul24(iz, ZS);
+            CellPair<C> p00, p10, p01, p11;
+            if constexpr (BUF) {
+                p00 = load_pair<C>(rsrc, voff, 0);
+                p10 = load_pair<C>(rsrc, voff, YS);
+                p01 = load_pair<C>(rsrc, voff, ZS);
+                p11 = load_pair<C>(rsrc, voff, YZ);
+            } else {
+                const char* vb = (const char*)A.vol;
+                p00 = load_pair_g<C>(vb, voff);
+                p10 = load_pair_g<C>(vb, voff + YS);
+                p01 = load_pair_g<C>(vb, voff + ZS);
+                p11 = load_pair_g<C>(vb, voff + YZ);
+            }
+            const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
+            const float w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
+            const float w000 = bx * w00, w100 = ax * w00, w010 = bx * w10, w110 = ax * w10;
+            const float w001 = bx * w01, w101 = ax * w01, w011 = bx * w11, w111 = ax * w11;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float t = acc[c];
+                t = fmaf(w000, p00.a[c], t);
+                t = fmaf(w100, p00.b[c], t);
+                t = fmaf(w010, p10.a[c], t);
+                t = fmaf(w110, p10.b[c], t);
+                t = fmaf(w001, p01.a[c], t);
+                t = fmaf(w101, p01.b[c], t);
+                t = fmaf(w011, p11.a[c], t);
+                t = fmaf(w111, p11.b[c], t);
+                acc[c] = t;
+            }
+        }
+    }
+    if (A.ms.seg > 1) {
+        __shared__ float segbuf[256 * C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
+        __syncthreads();
+        if (sid == 0)
+            for (int s2 = 1; s2 < A.ms.seg; ++s2)
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
+    }
+    const bool owner = valid && sid == 0;
+    const float dt = (float)g.dt;
+    if (owner && A.p_out) A.p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
+    if (A.partials) {
+        constexpr int NM = 5 + 3 * (C - 1);
+        double mo[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) mo[i] = 0.0;
+        if (owner) {
+            double yd = (double)A.y[iu + (size_t)g.nu * iv];
+            double pd = (double)(dt * acc[0]);
+            mo[0] = yd;
+            mo[1] = yd * yd;
+            mo[2] = pd;
+            mo[3] = yd * pd;
+            mo[4] = pd * pd;
+#pragma unroll
+            for (int k = 0; k < C - 1; ++k) {
+                if (k + 1 < A.kc) {
+                    double tk = (double)(dt * acc[k + 1]);
+                    mo[5 + 3 * k] = pd * tk;
+                    mo[6 + 3 * k] = yd * tk;
+                    mo[7 + 3 * k] = tk;
+                }
+            }
+        }
+        const int nm = 5 + 3 * (A.kc - 1);
+        block_sum_store<NM>(mo, nm, A.partials + (size_t)blockIdx.x * NM);
+    }
+}
+
+// --------------------------------------------------- brick backprojection
+// P^T r without global atomics: one workgroup owns a BX x BY x BZ brick of the
+// output held in LDS.  A sample at index-space point q feeds voxel v iff
+// floor(q_a) is v_a - 1 or v_a on every axis, i.e. q lies in the box
+// [b0 - 1, b0 + B) around the brick.  The workgroup takes every pixel whose
+// ray can cross that box (the detector bounding box of the box's projected
+// corners), marches only the ray's samples inside the box -- the same
+// sample points as the forward march -- and adds r * dt * weight to the
+// corners that fall in the brick with LDS atomics.  The brick is then written
+// once with plain stores, so no zeroing pass and no global atomics.
+constexpr int kBX = 16, kBY = 16, kBZ = 8;
+
+// Detector coordinates (mm along e_u, e_v) where the line from the source
+// through index-space point X meets the detector plane; false if X is not in
+// front of the source.
+__device__ __forceinline__ bool project_point(const RayGeom& g, const double X[3], double& u,
+                                              double& v)
+{
+    // solve S + t (X - S) = qc + u eu + v ev  (Cramer's rule)
+    double a[3], b[3], c[3], r[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = X[i] - g.qs[i];
+        b[i] = -g.eu[i];
+        c[i] = -g.ev[i];
+        r[i] = g.qc[i] - g.qs[i];
+    }
+    auto det3 = [](const double* x, const double* y, const double* z) {
+        return x[0] * (y[1] * z[2] - y[2] * z[1]) - y[0] * (x[1] * z[2] - x[2] * z[1]) +
+               z[0] * (x[1] * y[2] - x[2] * y[1]);
+    };
+    double D = det3(a, b, c);
+    if (D == 0.0) return false;
+    double t = det3(r, b, c) / D;
+    if (!(t > 0.0)) return false;
+    u = det3(a, r, c) / D;
+    v = det3(a, b, r) / D;
+    return true;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_backproject_brick(RayGeom g, int nbx, int nby,
+                                                           const R* __restrict__ resid,
+                                                           const R* __restrict__ p,
+                                                           const R* __restrict__ y, double a,
+                                                           double b, double scale,
+                                                           R* __restrict__ out, int nx, int ny,
+                                                           int nz)
+{
+    __shared__ R acc[kBZ * kBY * kBX];
+    __shared__ int box[4];
+    const int bid = blockIdx.x;
+    const int b0x = (bid % nbx) * kBX, b0y = ((bid / nbx) % nby) * kBY, b0z = (bid / (nbx * nby)) * kBZ;
+    for (int e = threadIdx.x; e < kBZ * kBY * kBX; e += 256) acc[e] = (R)0;
+    if (threadIdx.x == 0) {
+        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+        bool ok = true;
+        for (int c = 0; c < 8 && ok; ++c) {
+            double X[3] = {(double)(c & 1 ? b0x + kBX : b0x - 1), (double)(c & 2 ? b0y + kBY : b0y - 1),
+                           (double)(c & 4 ? b0z + kBZ : b0z - 1)};
+            double u, v;
+            ok = project_point(g, X, u, v);
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+            vmin = fmin(vmin, v);
+            vmax = fmax(vmax, v);
+        }
+        int iu0 = 0, iu1 = g.nu - 1, iv0 = 0, iv1 = g.nv - 1;
+        if (ok) {
+            iu0 = max(iu0, (int)fmax(floor((umin - g.u0) / g.du) - 1.0, -1.0));
+            iu1 = min(iu1, (int)fmin(ceil((umax - g.u0) / g.du) + 1.0, (double)g.nu));
+            iv0 = max(iv0, (int)fmax(floor((vmin - g.v0) / g.dv) - 1.0, -1.0));
+            iv1 = min(iv1, (int)fmin(ceil((vmax - g.v0) / g.dv) + 1.0, (double)g.nv));
+        }
+        box[0] = iu0;
+        box[1] = iu1;
+        box[2] = iv0;
+        box[3] = iv1;
+    }
+    __syncthreads();
+    const int iu0 = box[0], nub = box[1] - box[0] + 1, iv0 = box[2], nvb = box[3] - box[2] + 1;
+    const int nr = (nub > 0 && nvb > 0) ? nub * nvb : 0;
+    const R lo[3] = {(R)(b0x - 1), (R)(b0y - 1), (R)(b0z - 1)};
+    const R hi[3] = {(R)(b0x + kBX), (R)(b0y + kBY), (R)(b0z + kBZ)};
+    const R fn1[3] = {(R)(nx + 1), (R)(ny + 1), (R)(nz + 1)};
+    for (int rr = threadIdx.x; rr < nr; rr += 256) {
+        const int iu = iu0 + rr % nub, iv = iv0 + rr / nub;
+        const size_t pix = iu + (size_t)g.nu * iv;
+        R r = resid ? resid[pix] : (R)(scale * ((double)p[pix] - a * (double)y[pix] - b));
+        if (r == (R)0) continue;
+        RaySeg<R> rs = ray_segment<R>(g, iu, iv, 1, 0);
+        if (rs.count == 0) continue;
+        // samples of this ray inside the box (one sample of margin each side)
+        double mlo = 0.0, mhi = (double)(rs.count - 1);
+        bool miss = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            double q0 = (double)rs.q0[ax], d = (double)rs.dq[ax];
+            if (d != 0.0) {
+                double m1 = ((double)lo[ax] - q0) / d, m2 = ((double)hi[ax] - q0) / d;
+                mlo = fmax(mlo, floor(fmin(m1, m2)) - 1.0);
+                mhi = fmin(mhi, ceil(fmax(m1, m2)) + 1.0);
+            } else if (q0 < (double)lo[ax] - 1.0 || q0 > (double)hi[ax] + 1.0) {
+                miss = true;
+            }
+        }
+        if (miss || mlo > mhi) continue;
+        const R rw = r * (R)g.dt;
+        const R q0x = rs.q0[0] + (R)1, q0y = rs.q0[1] + (R)1, q0z = rs.q0[2] + (R)1;
+        for (int m = (int)mlo; m <= (int)mhi; ++m) {
+            const R fm = (R)m;
+            // identical arithmetic to the forward march (padded index space)
+            R qx = clampv(fma(fm, rs.dq[0], q0x), (R)0, fn1[0]);
+            R qy = clampv(fma(fm, rs.dq[1], q0y), (R)0, fn1[1]);
+            R qz = clampv(fma(fm, rs.dq[2], q0z), (R)0, fn1[2]);
+            const int ix = (int)qx - 1 - b0x, iy = (int)qy - 1 - b0y, iz = (int)qz - 1 - b0z;
+            if (ix < -1 || ix >= kBX || iy < -1 || iy >= kBY || iz < -1 || iz >= kBZ) continue;
+            const R ax = qx - floor(qx), ay = qy - floor(qy), az = qz - floor(qz);
+            const R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
+            const R wyz[4] = {by * bz, ay * bz, by * az, ay * az};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int dx = t & 1, dy = (t >> 1) & 1, dz = t >> 2;
+                const int tx = ix + dx, ty = iy + dy, tz = iz + dz;
+                if ((unsigned)tx < (unsigned)kBX && (unsigned)ty < (unsigned)kBY &&
+                    (unsigned)tz < (unsigned)kBZ)
+                    atomicAdd(&acc[(tz * kBY + ty) * kBX + tx], ((dx ? ax : bx) * wyz[dy + 2 * dz]) * rw);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBZ * kBY * kBX; e += 256) {
+        const int lx = e % kBX, ly = (e / kBX) % kBY, lz = e / (kBX * kBY);
+        const int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
+        if (gx < nx && gy < ny && gz < nz)
+            out[(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)] = acc[e];
     }
 }
 
@@ -472,7 +791,7 @@ template <typename R, typename S, typename F>
 __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
                                                   const S* __restrict__ mean,
                                                   const S* __restrict__ U, int K,
-                                                  Chan<double, 8> w, VoxGrid g, int px, int py,
+                                                  Chan<double, 8> w, VoxGrid g,
                                                   const R* __restrict__ gpad,
                                                   double* __restrict__ partials)
 {
@@ -483,7 +802,7 @@ __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
     if (i < g.nx && j < g.ny) {
         size_t N = (size_t)g.nx * g.ny * g.nz;
         size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
-        R gv = gpad[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))];
+        R gv = gpad[v];
         if (gv != (R)0) {
             R x[3], u[8][3];
 #pragma unroll
@@ -656,20 +975,26 @@ static Chan<double, 8> wvec(const double* w, int K)
     return c;
 }
 
-PadLayout make_pad(const pcr_grid& g, int C)
+PadLayout make_pad(const pcr_grid& g, int C, bool yfast)
 {
     PadLayout L;
     L.nx = g.n[0];
     L.ny = g.n[1];
     L.nz = g.n[2];
-    L.px = L.nx + 3;
-    L.py = L.ny + 3;
+    L.px = (yfast ? L.ny : L.nx) + 3;
+    L.py = (yfast ? L.nx : L.ny) + 3;
     L.pz = L.nz + 3;
     L.C = C;
+    L.yfast = yfast;
     return L;
 }
 
-RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G)
+bool prefer_yfast(const pcr_geom& G)
+{
+    return std::fabs(std::sin(G.angle_rad)) > std::fabs(std::cos(G.angle_rad));
+}
+
+RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
 {
     RayGeom r;
     double st = std::sin(G.angle_rad), ct = std::cos(G.angle_rad);
@@ -684,6 +1009,14 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G)
         r.eu[a] = eu[a] / g.spacing_mm[a];
         r.ev[a] = ev[a] / g.spacing_mm[a];
         r.lim[a] = (double)g.n[a];
+    }
+    if (swap_xy) {
+        std::swap(r.sp[0], r.sp[1]);
+        std::swap(r.qs[0], r.qs[1]);
+        std::swap(r.qc[0], r.qc[1]);
+        std::swap(r.eu[0], r.eu[1]);
+        std::swap(r.ev[0], r.ev[1]);
+        std::swap(r.lim[0], r.lim[1]);
     }
     r.u0 = -0.5 * (G.nu - 1) * G.du_mm + G.off_u_mm;
     r.v0 = -0.5 * (G.nv - 1) * G.dv_mm + G.off_v_mm;
@@ -702,6 +1035,19 @@ MarchShape choose_march_shape(const RayGeom& rg)
     long rays = (long)rg.nu * rg.nv;
     // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays when they are few
     ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
+    // tuning overrides (launch-shape sweeps): PCR_MARCH_TILE_U in {4..64},
+    // PCR_MARCH_SEG in {1, 2, 4}
+    if (const char* e = std::getenv("PCR_MARCH_TILE_U")) {
+        int v = std::atoi(e);
+        if (v == 4 || v == 8 || v == 16 || v == 32 || v == 64) ms.tile_u = v;
+    }
+    if (const char* e = std::getenv("PCR_MARCH_SEG")) {
+        int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) ms.seg = v;
+    }
+    ms.buffer_loads = true;
+    if (const char* e = std::getenv("PCR_MARCH_GLOBAL")) ms.buffer_loads = std::atoi(e) == 0;
+    if (ms.tile_u > 256 / ms.seg) ms.tile_u = 256 / ms.seg;
     return ms;
 }
 
@@ -765,10 +1111,14 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
 {
     dim3 grid = vox_grid(g), blk(64, 4);
     auto w = wvec(w_eff, K);
-#define PCR_WF(C, T)                                                                          \
-    k_warp_fused<R, S, F, C, T><<<grid, blk, 0, s>>>((const F*)f0, (const S*)mean, (const S*)U, \
-                                                     K, w, vox(g), L.px, L.py,                \
-                                                     (Chan<R, C>*)padded)
+    dim3 grid_yf((g.n[0] + 31) / 32, (g.n[1] + 31) / 32, g.n[2]);
+#define PCR_WF(C, T)                                                                              \
+    (L.yfast ? k_warp_fused_yf<R, S, F, C, T><<<grid_yf, 256, 0, s>>>(                            \
+                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py,           \
+                   (Chan<R, C>*)padded)                                                           \
+             : k_warp_fused<R, S, F, C, T><<<grid, blk, 0, s>>>((const F*)f0, (const S*)mean,      \
+                                                                (const S*)U, K, w, vox(g), L.px,  \
+                                                                L.py, (Chan<R, C>*)padded))
     if (!tangent) {
         switch (L.C) {
         case 1: PCR_WF(1, false); break;
@@ -842,14 +1192,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
 template <typename R>
 static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
                           const void* padded, const void* y, void* p_out, double* partials,
-                          hipStream_t s)
+                          double* moments, hipStream_t s)
 {
     int tiles_u = tiles_u_of(rg, ms);
     int blocks = march_blocks(rg, ms);
 #define PCR_MARCH(C)                                                                     \
     k_march<R, C><<<blocks, 256, 0, s>>>(rg, ms, tiles_u, (const Chan<R, C>*)padded, L.px, \
-                                         L.py, (float)L.nx, (float)L.ny, (float)L.nz, kc,  \
-                                         (const R*)y, (R*)p_out, partials)
+                                         L.py, (float)rg.lim[0], (float)rg.lim[1],         \
+                                         (float)rg.lim[2], kc, (const R*)y, (R*)p_out,     \
+                                         moments ? partials : nullptr)
     switch (L.C) {
     case 1: PCR_MARCH(1); break;
     case 2: PCR_MARCH(2); break;
@@ -858,15 +1209,59 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     default: return hipErrorInvalidValue;
     }
 #undef PCR_MARCH
+    if (moments) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_reduce<<<1, 256, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
+                            const void* padded, const void* y, void* p_out, double* partials,
+                            double* moments, unsigned* counter, hipStream_t s)
+{
+    MarchArgs A;
+    A.g = rg;
+    A.ms = ms;
+    A.tiles_u = tiles_u_of(rg, ms);
+    A.vol = padded;
+    A.vol_bytes = (unsigned)(L.cells() * (size_t)L.C * 4);
+    A.ys = L.px * L.C * 4;
+    A.zs = L.px * L.py * L.C * 4;
+    for (int a = 0; a < 3; ++a) A.fn1[a] = (float)(rg.lim[a] + 1.0);
+    A.kc = kc;
+    A.y = (const float*)y;
+    A.p_out = (float*)p_out;
+    A.partials = moments ? partials : nullptr;
+    A.moments = moments;
+    A.counter = counter;
+    int blocks = march_blocks(rg, ms);
+    const bool buf = ms.buffer_loads;
+#define PCR_MF(C) (buf ? k_march_f32<C, true><<<blocks, 256, 0, s>>>(A) : k_march_f32<C, false><<<blocks, 256, 0, s>>>(A))
+    switch (L.C) {
+    case 1: PCR_MF(1); break;
+    case 2: PCR_MF(2); break;
+    case 4: PCR_MF(4); break;
+    case 8: PCR_MF(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef PCR_MF
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !moments) return e;
+    k_reduce<<<1, 256, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
     return hipGetLastError();
 }
 
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, hipStream_t s)
+                        double* partials, double* moments, unsigned* counter, hipStream_t s)
 {
-    PCR_DISPATCH_R(compute, R, return march_r<R>(L, kc, rg, ms, padded, y, p_out, partials, s));
-    return hipSuccess;
+    if (compute == PCR_F32)
+        return march_f32(L, kc, rg, ms, padded, y, p_out, partials, moments, counter, s);
+    if (compute == PCR_F64)
+        return march_r<double>(L, kc, rg, ms, padded, y, p_out, partials, moments, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
@@ -876,31 +1271,30 @@ hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(pcr_dtype compute, const PadLayout& L, const RayGeom& rg,
-                              const MarchShape& ms, const void* resid, const void* p,
-                              const void* y, double a, double b, double scale, void* accum,
-                              hipStream_t s)
+hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeom& rg,
+                              const void* resid, const void* p, const void* y, double a, double b,
+                              double scale, void* out, hipStream_t s)
 {
-    int tiles_u = tiles_u_of(rg, ms);
-    int blocks = march_blocks(rg, ms);
+    const int nbx = (g.n[0] + kBX - 1) / kBX, nby = (g.n[1] + kBY - 1) / kBY,
+              nbz = (g.n[2] + kBZ - 1) / kBZ;
+    const unsigned blocks = (unsigned)(nbx * nby * nbz);
     PCR_DISPATCH_R(compute, R,
-        k_backproject<R><<<blocks, 256, 0, s>>>(rg, ms, tiles_u, (R*)accum, L.px, L.py,
-                                                (float)L.nx, (float)L.ny, (float)L.nz,
-                                                (const R*)resid, (const R*)p, (const R*)y, a, b,
-                                                scale));
+        k_backproject_brick<R><<<blocks, 256, 0, s>>>(rg, nbx, nby, (const R*)resid, (const R*)p,
+                                                      (const R*)y, a, b, scale, (R*)out, g.n[0],
+                                                      g.n[1], g.n[2]));
     return hipGetLastError();
 }
 
 hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
-                           const pcr_grid& g, const PadLayout& L, int K, const void* f0,
-                           const void* mean, const void* U, const double* w_eff,
-                           const void* gpad, double* partials, hipStream_t s)
+                           const pcr_grid& g, int K, const void* f0, const void* mean,
+                           const void* U, const double* w_eff, const void* gv, double* partials,
+                           hipStream_t s)
 {
     auto w = wvec(w_eff, K);
     PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S, PCR_DISPATCH_S(f0_dtype, F,
         k_contract<R, S, F><<<vox_grid(g), dim3(64, 4), 0, s>>>((const F*)f0, (const S*)mean,
-                                                                (const S*)U, K, w, vox(g), L.px,
-                                                                L.py, (const R*)gpad, partials))));
+                                                                (const S*)U, K, w, vox(g),
+                                                                (const R*)gv, partials))));
     return hipGetLastError();
 }
 

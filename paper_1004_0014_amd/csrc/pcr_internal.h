@@ -17,13 +17,22 @@ namespace pcr {
 // interleaved per cell.  Sample points are clamped to the support [-1, n] of
 // the interpolant per axis, so every tap of every sample is in bounds and
 // samples outside the support read only zero cells.
+//
+// The two in-plane axes may be stored in either order: x fastest
+// ([z][y][x], yfast = false) or y fastest ([z][x][y], yfast = true).  The
+// march then reads a geometry with x and y swapped, so that detector rows
+// (which run along e_u = (cos t, sin t, 0)) walk the fastest memory axis at
+// every gantry angle.  px, py are the padded dims in memory order.
 struct PadLayout {
     int nx, ny, nz;
-    int px, py, pz;      // nx+3, ny+3, nz+3
+    int px, py, pz;      // padded dims in memory order (fast, mid, slow)
     int C;               // channel stride (1, 2, 4 or 8)
+    bool yfast;
     size_t cells() const { return (size_t)px * py * pz; }
 };
-PadLayout make_pad(const pcr_grid& g, int C);
+PadLayout make_pad(const pcr_grid& g, int C, bool yfast = false);
+// y-fastest storage when the detector's u axis is closer to y than to x
+bool prefer_yfast(const pcr_geom& G);
 
 // Per-projection ray geometry in index space, computed on the host in FP64.
 // A ray from the source q_s towards pixel (iu, iv) has the index-space point
@@ -39,12 +48,14 @@ struct RayGeom {
     double dt;           // sample spacing (mm)
     int nu, nv;
 };
-RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G);
+// swap_xy: express the geometry in (y, x, z) index order (y-fastest layout).
+RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy = false);
 
 // Launch shape of the ray-march kernels.
 struct MarchShape {
     int tile_u;          // pixels along u covered by one wave (64 / tile_u rows)
     int seg;             // ray segments (threads) per ray: 1, 2 or 4
+    bool buffer_loads;   // FP32 march: raw buffer loads (else global loads)
 };
 MarchShape choose_march_shape(const RayGeom& rg);
 
@@ -76,26 +87,25 @@ hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padde
                         hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Ray march over kc used channels of a padded image; writes p (may be null)
-// and per-block moment partials (may be null; y required then).
+// and, when moments != null, the detector moments (y required then; uses
+// `partials` [march_blocks][kMaxMoments] and the zero-initialised `counter`).
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, hipStream_t s);
+                        double* partials, double* moments, unsigned* counter, hipStream_t s);
 // Fixed-order final sum of per-block partials: out[m] for m < nm.
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
                          hipStream_t s);
-// Scatter of the residual: accum (padded, 1 channel, pre-zeroed) +=
-// P^T r with r = resid (when resid != null) else scale * (p - a y - b).
-hipError_t launch_backproject(pcr_dtype compute, const PadLayout& L, const RayGeom& rg,
-                              const MarchShape& ms, const void* resid, const void* p,
-                              const void* y, double a, double b, double scale, void* accum,
-                              hipStream_t s);
-// Gradient contraction: partials[block][k] = sum_v g[v] (df/dx)[v] . u_k[v],
-// g read from the padded accumulator.
+// Backprojection out = P^T r (unpadded [N], fully overwritten) with r = resid
+// (when resid != null) else scale * (p - a y - b); x-fastest geometry.
+hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeom& rg,
+                              const void* resid, const void* p, const void* y, double a, double b,
+                              double scale, void* out, hipStream_t s);
+// Gradient contraction: partials[block][k] = sum_v g[v] (df/dx)[v] . u_k[v].
 int contract_blocks(const pcr_grid& g);
 hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
-                           const pcr_grid& g, const PadLayout& L, int K, const void* f0,
-                           const void* mean, const void* U, const double* w_eff,
-                           const void* gpad, double* partials, hipStream_t s);
+                           const pcr_grid& g, int K, const void* f0, const void* mean,
+                           const void* U, const double* w_eff, const void* gv, double* partials,
+                           hipStream_t s);
 hipError_t launch_warp_adjoint(pcr_dtype compute, const pcr_grid& g, const void* dvf,
                                const void* gv, void* out, hipStream_t s);
 // Fixed-point localisation; writes out[0..2] = p, out[3] = iterations,
