@@ -238,6 +238,76 @@ pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model,
                               int32_t max_iter, double p_out_mm[3], int32_t* iters,
                               void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of per-projection solves for many
+ * patient streams (each with its own grid, motion model, reference image,
+ * detector and warm-started w).  A worker thread keeps up to max_slots solves
+ * in flight, one HIP stream each; every solve advances by one line-search
+ * trial per turn and new requests take slots as soon as solves finish, so
+ * requests that arrive while others run overlap with them on the device.
+ * Each solve runs exactly the steps of pcr_reconstruct_from_projection
+ * (fused gradient, deterministic reductions): its result is bitwise the same
+ * alone and in the mix.  Warm start (section 4): each stream's next solve
+ * starts from its previous result.
+ * ------------------------------------------------------------------------ */
+typedef struct pcr_server pcr_server;
+
+typedef struct pcr_server_opts {
+    size_t hbm_budget_bytes;  /* server-owned device memory limit: stream copies of
+                                 reference images and models plus per-slot scratch */
+    int32_t max_slots;        /* solves in flight at once (1..64) */
+    int32_t drop_stale;       /* nonzero: a queued (not yet started) request is dropped
+                                 when a newer one of the same stream arrives */
+} pcr_server_opts;
+
+typedef struct pcr_result {
+    int64_t req_id;
+    int32_t stream_id;
+    int32_t status;           /* solve status (PCR_OK / PCR_ENOCONV / error), or
+                                 PCR_EBUSY when the request was dropped as stale */
+    int32_t iterations, trials, K, fp_status;
+    double w0[8];             /* warm start the solve began from */
+    double w[8];              /* result */
+    double ab[2], J, tumor_mm[3];
+    double t_submit_s, t_start_s, t_done_s;   /* steady-clock seconds */
+} pcr_result;
+
+/* Creates the server and its worker thread on the current device. */
+pcr_status pcr_server_create(const pcr_server_opts* opts, pcr_server** out);
+/* Stops the worker (in-flight solves finish first) and frees all memory. */
+void pcr_server_destroy(pcr_server* srv);
+/* Registers a stream: copies f0 [N] (f0_dtype) and the model (mean, U, scale)
+ * from the caller's device memory into server-owned memory, so the caller may
+ * free its copies.  opts: solve options of every request of the stream
+ * (grad_mode must be PCR_GRAD_FUSED; compute is FP32); w0: first warm start.
+ * Admission by HBM footprint: PCR_EBUSY (nothing allocated) when the stream's
+ * copies plus per-slot scratch large enough for every admitted grid would
+ * exceed hbm_budget_bytes.  Synchronises the copies. */
+pcr_status pcr_server_add_stream(pcr_server* srv, const pcr_grid* grid, const pcr_model* model,
+                                 pcr_dtype f0_dtype, const void* f0_dev,
+                                 const pcr_solve_opts* opts, const double* w0,
+                                 int32_t* stream_id);
+/* Removes a stream once its queued and in-flight requests are done or dropped. */
+pcr_status pcr_server_remove_stream(pcr_server* srv, int32_t stream_id);
+/* Queues one projection y_dev [nv][nu] FP32 at geometry `geom` for the stream.
+ * y_dev is not copied: it must stay valid until the request's result has been
+ * polled.  Returns the request id. */
+pcr_status pcr_server_submit(pcr_server* srv, int32_t stream_id, const void* y_dev,
+                             const pcr_geom* geom, int64_t* req_id);
+/* Moves up to max finished results to out[] (oldest first); waits up to
+ * wait_ms for at least one when none is ready.  *n = number written. */
+pcr_status pcr_server_poll(pcr_server* srv, pcr_result* out, int32_t max, int32_t* n,
+                           int32_t wait_ms);
+/* Waits until no request is queued or in flight (timeout_ms < 0: forever);
+ * PCR_EBUSY on timeout. */
+pcr_status pcr_server_drain(pcr_server* srv, int32_t timeout_ms);
+/* Snapshot / restore of a stream's warm start (checkpoint of the serving
+ * state; the model itself is re-registered from its source). */
+pcr_status pcr_server_get_w(pcr_server* srv, int32_t stream_id, double* w_out);
+pcr_status pcr_server_set_w(pcr_server* srv, int32_t stream_id, const double* w);
+/* Device bytes held (stream copies + slot scratch) and budget accounting. */
+size_t pcr_server_device_bytes(const pcr_server* srv);
+
 /* Opt-in kernel timing (tracing).  While enabled, every kernel the library
  * launches is bracketed by two HIP events on the stream it runs on.  Enabling
  * resets the totals.  pcr_profile_read resolves pending events (waiting for

@@ -63,6 +63,26 @@ class SolveStats(C.Structure):
         return d
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("req_id", C.c_int64), ("stream_id", C.c_int32), ("status", C.c_int32),
+                ("iterations", C.c_int32), ("trials", C.c_int32), ("K", C.c_int32),
+                ("fp_status", C.c_int32), ("w0", C.c_double * 8), ("w", C.c_double * 8),
+                ("ab", C.c_double * 2), ("J", C.c_double), ("tumor_mm", C.c_double * 3),
+                ("t_submit_s", C.c_double), ("t_start_s", C.c_double), ("t_done_s", C.c_double)]
+
+    def as_dict(self):
+        K = self.K
+        return {"req_id": self.req_id, "stream_id": self.stream_id, "status": self.status,
+                "iterations": self.iterations, "trials": self.trials, "fp_status": self.fp_status,
+                "w0": list(self.w0[:K]), "w": list(self.w[:K]), "ab": list(self.ab), "J": self.J,
+                "tumor_mm": list(self.tumor_mm), "t_submit_s": self.t_submit_s,
+                "t_start_s": self.t_start_s, "t_done_s": self.t_done_s}
+
+
 _lib = None
 _P = C.c_void_p
 _PD = C.POINTER(C.c_double)
@@ -96,6 +116,18 @@ def lib():
             "pcr_localize_tumor": (C.c_int32, [G, Md, _PD, _PD, C.c_double, C.c_int32, _PD,
                                                C.POINTER(C.c_int32), _P]),
             "pcr_warp_contract": (C.c_int32, [G, Md, C.c_int, _P, _PD, C.c_int, _P, _PD, _P]),
+            "pcr_server_create": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(_P)]),
+            "pcr_server_destroy": (None, [_P]),
+            "pcr_server_add_stream": (C.c_int32, [_P, G, Md, C.c_int, _P, C.POINTER(SolveOpts), _PD,
+                                                  C.POINTER(C.c_int32)]),
+            "pcr_server_remove_stream": (C.c_int32, [_P, C.c_int32]),
+            "pcr_server_submit": (C.c_int32, [_P, C.c_int32, _P, Gm, C.POINTER(C.c_int64)]),
+            "pcr_server_poll": (C.c_int32, [_P, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32),
+                                            C.c_int32]),
+            "pcr_server_drain": (C.c_int32, [_P, C.c_int32]),
+            "pcr_server_get_w": (C.c_int32, [_P, C.c_int32, _PD]),
+            "pcr_server_set_w": (C.c_int32, [_P, C.c_int32, _PD]),
+            "pcr_server_device_bytes": (C.c_size_t, [_P]),
             "pcr_profile_enable": (None, [C.c_int32]),
             "pcr_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_char_p), _PD,
                                              C.POINTER(C.c_int64)]),
@@ -318,3 +350,66 @@ def profile_read() -> dict:
     cnt = (C.c_int64 * n)()
     k = lib().pcr_profile_read(n, names, tot, cnt)
     return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(k, n)) if cnt[i] > 0}
+
+
+class Server:
+    """Serving engine (pcr_server_*): continuous batching of per-projection
+    solves for many streams.  Streams' reference images and models are copied
+    into server-owned device memory at add_stream."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0)
+        h = C.c_void_p()
+        _check(lib().pcr_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._geoms = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pcr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_stream(self, grid, model: DeviceModel, f0: torch.Tensor, opts: SolveOpts, w0) -> int:
+        """Returns the stream id; raises PCRError with status PCR_EBUSY when
+        the HBM budget would be exceeded."""
+        g = make_grid(grid)
+        sid = C.c_int32(-1)
+        _check(lib().pcr_server_add_stream(self._h, C.byref(g), C.byref(model.struct), _dtype(f0),
+                                           _ptr(f0), C.byref(opts), _dd(w0), C.byref(sid)))
+        return sid.value
+
+    def remove_stream(self, sid: int):
+        _check(lib().pcr_server_remove_stream(self._h, sid))
+
+    def submit(self, sid: int, y: torch.Tensor, geom) -> int:
+        G = make_geom(geom)
+        rid = C.c_int64(-1)
+        _check(lib().pcr_server_submit(self._h, sid, _ptr(y), C.byref(G), C.byref(rid)))
+        return rid.value
+
+    def poll(self, max_results: int = 256, wait_ms: int = 0):
+        buf = (Result * max_results)()
+        n = C.c_int32(0)
+        _check(lib().pcr_server_poll(self._h, buf, max_results, C.byref(n), wait_ms))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def drain(self, timeout_ms: int = -1):
+        _check(lib().pcr_server_drain(self._h, timeout_ms))
+
+    def get_w(self, sid: int, K: int):
+        w = (C.c_double * K)()
+        _check(lib().pcr_server_get_w(self._h, sid, w))
+        return list(w)
+
+    def set_w(self, sid: int, w):
+        _check(lib().pcr_server_set_w(self._h, sid, _dd(w)))
+
+    @property
+    def device_bytes(self) -> int:
+        return lib().pcr_server_device_bytes(self._h)

@@ -1,5 +1,6 @@
 // C ABI of the reconstruction library: validation, device scratch, the
-// solver context and the per-projection solve (section 2.2 of Li et al.).
+// kernel profiler, the stateless entry points, the solver context and the
+// per-projection solve (section 2.2 of Li et al.).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,17 +12,18 @@
 #include <string>
 #include <vector>
 
-#include "pcr.h"
-#include "pcr_internal.h"
+#include "host.h"
 
 using namespace pcr;
 
-#define PCR_VERSION_STRING "pcr 0.1.0 (gfx950)"
+#define PCR_VERSION_STRING "pcr 0.2.0 (gfx950)"
+
+namespace pcr {
 
 // ------------------------------------------------------------- errors ----
 static thread_local std::string g_err;
 
-static pcr_status fail(pcr_status code, const char* fmt, ...)
+pcr_status fail(pcr_status code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -32,22 +34,8 @@ static pcr_status fail(pcr_status code, const char* fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(e_ == hipErrorOutOfMemory ? PCR_ENOMEM : PCR_EDEVICE, "%s: %s (%s:%d)", \
-                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
-    } while (0)
-
-#define PCR_TRY(expr)                                                                        \
-    do {                                                                                     \
-        pcr_status s_ = (expr);                                                              \
-        if (s_ != PCR_OK) return s_;                                                         \
-    } while (0)
-
 // --------------------------------------------------------- validation ----
-static size_t dtype_size(pcr_dtype d)
+size_t dtype_size(pcr_dtype d)
 {
     switch (d) {
     case PCR_F32: return 4;
@@ -58,7 +46,7 @@ static size_t dtype_size(pcr_dtype d)
     return 0;
 }
 
-static pcr_status check_grid(const pcr_grid* g)
+pcr_status check_grid(const pcr_grid* g)
 {
     if (!g) return fail(PCR_EINVAL, "grid is NULL");
     for (int a = 0; a < 3; ++a) {
@@ -67,14 +55,14 @@ static pcr_status check_grid(const pcr_grid* g)
             return fail(PCR_EINVAL, "grid spacing[%d] must be finite and > 0", a);
         if (!std::isfinite(g->origin_mm[a])) return fail(PCR_EINVAL, "grid origin must be finite");
     }
-    if (g->n[2] > 65535 || (g->n[1] + 3) / 4 > 65535)
+    if (g->n[2] > 65535 || (g->n[1] + 31) / 32 > 65535)
         return fail(PCR_EINVAL, "grid n = (%d, %d, %d) exceeds the launch limits", g->n[0], g->n[1], g->n[2]);
     double cells = (double)(g->n[0] + 3) * (g->n[1] + 3) * (g->n[2] + 3);
     if (cells > 2.0e9) return fail(PCR_EINVAL, "grid too large (%.3g padded cells)", cells);
     return PCR_OK;
 }
 
-static pcr_status check_geom(const pcr_geom* G)
+pcr_status check_geom(const pcr_geom* G)
 {
     if (!G) return fail(PCR_EINVAL, "geometry is NULL");
     const double v[] = {G->angle_rad, G->sad_mm, G->sdd_mm, G->du_mm, G->dv_mm, G->off_u_mm,
@@ -94,19 +82,19 @@ static pcr_status check_geom(const pcr_geom* G)
     return PCR_OK;
 }
 
-static pcr_status check_compute(pcr_dtype d)
+pcr_status check_compute(pcr_dtype d)
 {
     if (d != PCR_F32 && d != PCR_F64) return fail(PCR_EINVAL, "compute dtype must be F32 or F64");
     return PCR_OK;
 }
 
-static pcr_status check_storage(pcr_dtype d)
+pcr_status check_storage(pcr_dtype d)
 {
     if (dtype_size(d) == 0) return fail(PCR_EINVAL, "unknown dtype %d", (int)d);
     return PCR_OK;
 }
 
-static pcr_status check_model(const pcr_model* m)
+pcr_status check_model(const pcr_model* m)
 {
     if (!m) return fail(PCR_EINVAL, "model is NULL");
     if (m->K < 1 || m->K > 8) return fail(PCR_EINVAL, "model K = %d must be in 1..8", m->K);
@@ -118,7 +106,7 @@ static pcr_status check_model(const pcr_model* m)
     return PCR_OK;
 }
 
-static pcr_status check_finite(const double* v, int n, const char* what)
+pcr_status check_finite(const double* v, int n, const char* what)
 {
     if (!v) return fail(PCR_EINVAL, "%s is NULL", what);
     for (int i = 0; i < n; ++i)
@@ -126,90 +114,81 @@ static pcr_status check_finite(const double* v, int n, const char* what)
     return PCR_OK;
 }
 
-static void effective_w(const pcr_model& m, const double* w, double* w_eff)
+pcr_status check_opts(const pcr_solve_opts* o)
 {
-    for (int k = 0; k < m.K; ++k) w_eff[k] = w[k] * (m.scale ? m.scale[k] : 1.0);
-}
-
-static int channels_for(int kc)
-{
-    return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+    if (!o) return fail(PCR_EINVAL, "opts is NULL");
+    if (o->max_iter < 0 || o->max_backtracks < 1) return fail(PCR_EINVAL, "bad iteration limits");
+    if (!(o->sigma > 0 && o->sigma < 1)) return fail(PCR_EINVAL, "sigma must be in (0, 1)");
+    if (!(o->beta > 0 && o->beta < 1)) return fail(PCR_EINVAL, "beta must be in (0, 1)");
+    if (!(o->eps_g >= 0) || !std::isfinite(o->eps_g)) return fail(PCR_EINVAL, "bad eps_g");
+    if (!(o->fixed_mu >= 0) || !std::isfinite(o->fixed_mu)) return fail(PCR_EINVAL, "bad fixed_mu");
+    if (o->fixed_mu == 0 && !(o->step0 > 0 && std::isfinite(o->step0)))
+        return fail(PCR_EINVAL, "step0 must be > 0");
+    if (o->grad_mode != PCR_GRAD_FUSED && o->grad_mode != PCR_GRAD_ADJOINT)
+        return fail(PCR_EINVAL, "unknown grad_mode %d", o->grad_mode);
+    if (o->localize) {
+        PCR_TRY(check_finite(o->p_ref_mm, 3, "p_ref_mm"));
+        if (!(o->fp_tol_mm > 0) || o->fp_max_iter < 1) return fail(PCR_EINVAL, "bad fixed-point options");
+    }
+    return PCR_OK;
 }
 
 // ------------------------------------------------------- device scratch --
-// Grow-only device buffer owned by the library.
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    int device = -1;
-    pcr_status ensure(size_t need, int dev, hipStream_t s)
-    {
-        need = (need + 255) & ~(size_t)255;
-        if (p && bytes >= need && device == dev) return PCR_OK;
-        if (p) {
-            HIP_TRY(hipStreamSynchronize(s));
-            HIP_TRY(hipFree(p));
-            p = nullptr;
-            bytes = 0;
-        }
-        HIP_TRY(hipMalloc(&p, need));
-        bytes = need;
-        device = dev;
-        return PCR_OK;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
+pcr_status DevBuf::ensure(size_t need, int dev, hipStream_t s)
+{
+    need = (need + 255) & ~(size_t)255;
+    if (p && bytes >= need && device == dev) return PCR_OK;
+    if (p) {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipFree(p));
         p = nullptr;
         bytes = 0;
     }
-};
-
-struct HostBuf {
-    double* p = nullptr;
-    size_t n = 0;
-    pcr_status ensure(size_t need)
-    {
-        if (p && n >= need) return PCR_OK;
-        if (p) HIP_TRY(hipHostFree(p));
-        p = nullptr;
-        HIP_TRY(hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault));
-        n = need;
-        return PCR_OK;
-    }
-    void release()
-    {
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        n = 0;
-    }
-};
-
-// Per-thread scratch of the stateless entry points.
-struct TlsScratch {
-    DevBuf pad, small;
-    HostBuf host;
-    ~TlsScratch()
-    {
-        pad.release();
-        small.release();
-        host.release();
-    }
-};
-static thread_local TlsScratch tls;
-
-static pcr_status current_device(int* dev)
-{
-    HIP_TRY(hipGetDevice(dev));
+    HIP_TRY(hipMalloc(&p, need));
+    bytes = need;
+    device = dev;
     return PCR_OK;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+pcr_status HostBuf::ensure(size_t need)
+{
+    if (p && n >= need) return PCR_OK;
+    if (p) HIP_TRY(hipHostFree(p));
+    p = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault));
+    n = need;
+    return PCR_OK;
+}
+
+void HostBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+}
+
+void Scratch::release()
+{
+    volc.release();
+    vol1.release();
+    acc1.release();
+    p.release();
+    partials.release();
+    moments.release();
+    host.release();
 }
 
 // ----------------------------------------------------------- profiler ----
 // Opt-in per-kernel timing: every launch of the library is bracketed by two
 // HIP events on the stream it runs on; durations are resolved when read.
 namespace prof {
-enum Id { WARP, MARCH, REDUCE, BACKPROJ, CONTRACT, LOCALIZE, ZERO, PAD, UNPAD, COMPOSE, WARP_PLAIN,
-          WARP_ADJ, NKERN };
 static const char* kNames[NKERN] = {"warp_fused", "march", "reduce", "backproject", "contract",
                                     "localize", "zero", "pad", "unpad", "compose", "warp",
                                     "warp_adjoint"};
@@ -237,34 +216,30 @@ static hipEvent_t get_event()
     return e;
 }
 
-struct Scope {
-    hipStream_t s;
-    int id;
-    hipEvent_t a = nullptr;
-    Scope(int id_, hipStream_t s_) : s(s_), id(id_)
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!enabled) return;
-        a = get_event();
-        if (a && hipEventRecord(a, s) != hipSuccess) {
-            pool.push_back(a);
-            a = nullptr;
-        }
+Scope::Scope(int id_, hipStream_t s_) : s(s_), id(id_)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    if (!enabled) return;
+    a = get_event();
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+        pool.push_back(a);
+        a = nullptr;
     }
-    ~Scope()
-    {
-        if (!a) return;
-        std::lock_guard<std::mutex> lk(mu);
-        hipEvent_t b = get_event();
-        if (!b || hipEventRecord(b, s) != hipSuccess) {
-            pool.push_back(a);
-            if (b) pool.push_back(b);
-            ++dropped;
-            return;
-        }
-        pending.push_back({a, b, id});
+}
+
+Scope::~Scope()
+{
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(mu);
+    hipEvent_t b = get_event();
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+        pool.push_back(a);
+        if (b) pool.push_back(b);
+        ++dropped;
+        return;
     }
-};
+    pending.push_back({a, b, id});
+}
 
 static void flush_locked()
 {
@@ -283,10 +258,173 @@ static void flush_locked()
 }
 }  // namespace prof
 
-#define PROF(id, s) prof::Scope prof_scope_##__LINE__(prof::id, s)
+// ------------------------------------------------------------ evaluator --
+pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
+{
+    y = y_;
+    mode = mode_;
+    rg = make_ray_geom(*grid, G);
+    ms = choose_march_shape(rg);
+    M = G.nu * G.nv;
+    blocks = march_blocks(rg, ms);
+    const bool yfast = prefer_yfast(G);
+    const int Cc = channels_for(model->K + 1);
+    const size_t esz = dtype_size(compute);
+    sc->Lc = make_pad(*grid, Cc, yfast);
+    sc->L1 = make_pad(*grid, 1);
+    rgc = make_ray_geom(*grid, G, yfast);
+    msc = choose_march_shape(rgc);
+    blocksc = march_blocks(rgc, msc);
+    const int dev = sc->device;
+    if (mode == PCR_GRAD_FUSED) {
+        bool fresh = sc->volc.p == nullptr || sc->volc.bytes < sc->Lc.cells() * Cc * esz;
+        PCR_TRY(sc->volc.ensure(sc->Lc.cells() * Cc * esz, dev, s));
+        bool same_grid = sc->volc_grid[0] == grid->n[0] && sc->volc_grid[1] == grid->n[1] &&
+                         sc->volc_grid[2] == grid->n[2];
+        if (fresh || !same_grid || sc->volc_yfast != (int)yfast) {
+            // border cells of one layout (or grid) are interior cells of another
+            PROF(ZERO, s);
+            HIP_TRY(launch_zero(sc->volc.p, sc->volc.bytes, s));
+            sc->volc_yfast = (int)yfast;
+            for (int a = 0; a < 3; ++a) sc->volc_grid[a] = grid->n[a];
+        }
+    } else {
+        size_t b1 = sc->L1.cells() * esz;
+        bool fresh = sc->vol1.p == nullptr || sc->vol1.bytes < b1;
+        PCR_TRY(sc->vol1.ensure(b1, dev, s));
+        if (fresh) {
+            PROF(ZERO, s);
+            HIP_TRY(launch_zero(sc->vol1.p, sc->vol1.bytes, s));
+        }
+        PCR_TRY(sc->acc1.ensure((size_t)grid->n[0] * grid->n[1] * grid->n[2] * esz, dev, s));
+        PCR_TRY(sc->p.ensure((size_t)M * esz, dev, s));
+    }
+    int cblocks = contract_blocks(*grid);
+    PCR_TRY(sc->partials.ensure((size_t)std::max(std::max(blocks, blocksc), cblocks) * kMaxMoments *
+                                    sizeof(double),
+                                dev, s));
+    PCR_TRY(sc->moments.ensure(kMaxMoments * sizeof(double), dev, s));
+    PCR_TRY(sc->host.ensure(kMaxMoments));
+    return PCR_OK;
+}
+
+pcr_status Evaluator::enqueue_eval(const double* w)
+{
+    double w_eff[8];
+    effective_w(*model, w, w_eff);
+    const int K = model->K;
+    const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
+    double* mom = (double*)sc->moments.p;
+    if (mode == PCR_GRAD_FUSED) {
+        {
+            PROF(WARP, s);
+            HIP_TRY(launch_warp_fused(compute, model->storage, f0_dtype, *grid, sc->Lc, K, true, f0,
+                                      model->mean, model->U, w_eff, sc->volc.p, s));
+        }
+        {
+            PROF(MARCH, s);
+            HIP_TRY(launch_march(compute, sc->Lc, kc, rgc, msc, sc->volc.p, y, nullptr,
+                                 (double*)sc->partials.p, mom, nullptr, s));
+        }
+    } else {
+        {
+            PROF(WARP, s);
+            HIP_TRY(launch_warp_fused(compute, model->storage, f0_dtype, *grid, sc->L1, K, false, f0,
+                                      model->mean, model->U, w_eff, sc->vol1.p, s));
+        }
+        {
+            PROF(MARCH, s);
+            HIP_TRY(launch_march(compute, sc->L1, 1, rg, ms, sc->vol1.p, y, sc->p.p,
+                                 (double*)sc->partials.p, mom, nullptr, s));
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(sc->host.p, mom, n_moments(kc) * sizeof(double), hipMemcpyDeviceToHost, s));
+    return PCR_OK;
+}
+
+void Evaluator::collect(Moments& out) const
+{
+    const int kc = mode == PCR_GRAD_FUSED ? model->K + 1 : 1;
+    std::memset(out.m, 0, sizeof out.m);
+    std::memcpy(out.m, sc->host.p, n_moments(kc) * sizeof(double));
+    out.M = (double)M;
+    out.K = model->K;
+}
+
+pcr_status Evaluator::eval_sync(const double* w, Moments& out)
+{
+    PCR_TRY(enqueue_eval(w));
+    HIP_TRY(hipStreamSynchronize(s));
+    collect(out);
+    return PCR_OK;
+}
+
+pcr_status Evaluator::grad_adjoint(const double* w, double a, double b, double* grad)
+{
+    double w_eff[8];
+    effective_w(*model, w, w_eff);
+    const int K = model->K;
+    {
+        PROF(BACKPROJ, s);
+        HIP_TRY(launch_backproject(compute, *grid, rg, nullptr, sc->p.p, y, a, b, 2.0, sc->acc1.p, s));
+    }
+    {
+        PROF(CONTRACT, s);
+        HIP_TRY(launch_contract(compute, model->storage, f0_dtype, *grid, K, f0, model->mean, model->U,
+                                w_eff, sc->acc1.p, (double*)sc->partials.p, s));
+    }
+    {
+        PROF(REDUCE, s);
+        HIP_TRY(launch_reduce((const double*)sc->partials.p, contract_blocks(*grid), 8, K,
+                              (double*)sc->moments.p, s));
+    }
+    HIP_TRY(hipMemcpyAsync(sc->host.p, sc->moments.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < K; ++k) grad[k] = sc->host.p[k];
+    return PCR_OK;
+}
+
+}  // namespace pcr
+
+// Per-thread scratch of the stateless entry points.
+namespace {
+struct TlsScratch {
+    DevBuf pad, small;
+    HostBuf host;
+    ~TlsScratch()
+    {
+        pad.release();
+        small.release();
+        host.release();
+    }
+};
+thread_local TlsScratch tls;
+
+pcr_status current_device(int* dev)
+{
+    HIP_TRY(hipGetDevice(dev));
+    return PCR_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && (prev == dev || hipSetDevice(dev) == hipSuccess)) ok = true;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
 
 // ============================================================ C ABI =======
 extern "C" {
+
+const char* pcr_version(void) { return PCR_VERSION_STRING; }
+const char* pcr_last_error(void) { return pcr::g_err.c_str(); }
 
 void pcr_profile_enable(int32_t on)
 {
@@ -314,9 +452,6 @@ int32_t pcr_profile_read(int32_t max, const char** names, double* total_ms, int6
     }
     return prof::NKERN;
 }
-
-const char* pcr_version(void) { return PCR_VERSION_STRING; }
-const char* pcr_last_error(void) { return g_err.c_str(); }
 
 void pcr_solve_opts_default(pcr_solve_opts* o)
 {
@@ -346,11 +481,9 @@ pcr_status pcr_dvf_compose(const pcr_grid* grid, const pcr_model* model, const d
     double w_eff[8];
     effective_w(*model, w_host, w_eff);
     hipStream_t s = (hipStream_t)stream;
-    {
-        PROF(COMPOSE, s);
-        HIP_TRY(launch_compose(compute, model->storage, *grid, model->K, model->mean, model->U, w_eff,
-                               dvf_dev, s));
-    }
+    PROF(COMPOSE, s);
+    HIP_TRY(launch_compose(compute, model->storage, *grid, model->K, model->mean, model->U, w_eff,
+                           dvf_dev, s));
     return PCR_OK;
 }
 
@@ -363,10 +496,8 @@ pcr_status pcr_warp_volume(const pcr_grid* grid, pcr_dtype f0_dtype, const void*
     if (!f0_dev || !dvf_dev || !f_dev) return fail(PCR_EINVAL, "NULL device pointer");
     if (f_dev == f0_dev) return fail(PCR_EINVAL, "f_dev must not alias f0_dev");
     hipStream_t s = (hipStream_t)stream;
-    {
-        PROF(WARP_PLAIN, s);
-        HIP_TRY(launch_warp_plain(compute, f0_dtype, *grid, f0_dev, dvf_dev, f_dev, s));
-    }
+    PROF(WARP_PLAIN, s);
+    HIP_TRY(launch_warp_plain(compute, f0_dtype, *grid, f0_dev, dvf_dev, f_dev, s));
     return PCR_OK;
 }
 
@@ -382,10 +513,8 @@ pcr_status pcr_warp_adjoint(const pcr_grid* grid, pcr_dtype compute, const void*
         PROF(ZERO, s);
         HIP_TRY(launch_zero(out_dev, N * dtype_size(compute), s));
     }
-    {
-        PROF(WARP_ADJ, s);
-        HIP_TRY(launch_warp_adjoint(compute, *grid, dvf_dev, g_dev, out_dev, s));
-    }
+    PROF(WARP_ADJ, s);
+    HIP_TRY(launch_warp_adjoint(compute, *grid, dvf_dev, g_dev, out_dev, s));
     return PCR_OK;
 }
 
@@ -412,11 +541,8 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     }
     RayGeom rg = make_ray_geom(*grid, *geom);
     MarchShape ms = choose_march_shape(rg);
-    {
-        PROF(MARCH, s);
-        HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr,
-                             nullptr, s));
-    }
+    PROF(MARCH, s);
+    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, nullptr, s));
     return PCR_OK;
 }
 
@@ -429,11 +555,8 @@ pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom, 
     if (!resid_dev || !vol_dev) return fail(PCR_EINVAL, "NULL device pointer");
     hipStream_t s = (hipStream_t)stream;
     RayGeom rg = make_ray_geom(*grid, *geom);
-    {
-        PROF(BACKPROJ, s);
-        HIP_TRY(launch_backproject(compute, *grid, rg, resid_dev, nullptr, nullptr, 0.0, 0.0, 1.0,
-                                   vol_dev, s));
-    }
+    PROF(BACKPROJ, s);
+    HIP_TRY(launch_backproject(compute, *grid, rg, resid_dev, nullptr, nullptr, 0.0, 0.0, 1.0, vol_dev, s));
     return PCR_OK;
 }
 
@@ -511,229 +634,9 @@ struct pcr_ctx {
     double scale[8];
     pcr_dtype f0_dtype, compute;
     const void* f0;
-    int device;
-    PadLayout Lc, L1;     // fused (K+1 channels) and single-channel layouts
-    int volc_yfast = -1;  // layout currently held by volc (-1: not zeroed for any)
-    DevBuf volc, vol1, acc1, p, partials, moments, counter;
-    HostBuf host;
-    ~pcr_ctx()
-    {
-        counter.release();
-        volc.release();
-        vol1.release();
-        acc1.release();
-        p.release();
-        partials.release();
-        moments.release();
-        host.release();
-    }
+    Scratch sc;
+    ~pcr_ctx() { sc.release(); }
 };
-
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) == hipSuccess && (prev == dev || hipSetDevice(dev) == hipSuccess)) ok = true;
-    }
-    ~DeviceGuard()
-    {
-        if (ok && prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-struct Moments {
-    double m[kMaxMoments];
-    double M;
-    int K;
-    // J(a, b) = sum (p - a y - b)^2 expanded in the moments (eq. (2))
-    double J(double a, double b) const
-    {
-        return m[4] - 2 * a * m[3] - 2 * b * m[2] + a * a * m[1] + 2 * a * b * m[0] + b * b * M;
-    }
-    // dJ/dw_eff_k = 2 sum (p - a y - b) t_k (gradient of section 2.2)
-    double grad(int k, double a, double b) const
-    {
-        return 2.0 * (m[5 + 3 * k] - a * m[6 + 3 * k] - b * m[7 + 3 * k]);
-    }
-    // step 2, eq. (4): least-squares (a, b) for Y = [y, 1]; singular Y^T Y
-    // (constant y) gives a = 0 and b = mean(p)
-    void step2(double* a, double* b) const
-    {
-        double sy = m[0], syy = m[1], sp = m[2], syp = m[3];
-        double D = syy * M - sy * sy;
-        if (!(D > 1e-12 * syy * M)) {
-            *a = 0.0;
-            *b = M > 0 ? sp / M : 0.0;
-            return;
-        }
-        *a = (M * syp - sy * sp) / D;
-        *b = (syy * sp - sy * syp) / D;
-    }
-};
-
-struct Solver {
-    pcr_ctx* c;
-    hipStream_t s;
-    RayGeom rg;      // x-fastest geometry (adjoint path)
-    RayGeom rgc;     // geometry in the fused image's layout
-    MarchShape ms, msc;
-    int M;
-    int blocks, blocksc;
-    const void* y;
-
-    pcr_status prepare(const void* y_, const pcr_geom& G, int mode)
-    {
-        y = y_;
-        rg = make_ray_geom(c->grid, G);
-        ms = choose_march_shape(rg);
-        M = G.nu * G.nv;
-        blocks = march_blocks(rg, ms);
-        const bool yfast = prefer_yfast(G);
-        c->Lc = make_pad(c->grid, c->Lc.C, yfast);
-        rgc = make_ray_geom(c->grid, G, yfast);
-        msc = choose_march_shape(rgc);
-        blocksc = march_blocks(rgc, msc);
-        if (mode == PCR_GRAD_FUSED && c->volc_yfast != (int)yfast) {
-            // border cells of one layout are interior cells of the other
-            {
-                PROF(ZERO, s);
-                HIP_TRY(launch_zero(c->volc.p, c->volc.bytes, s));
-            }
-            c->volc_yfast = (int)yfast;
-        }
-        int cblocks = contract_blocks(c->grid);
-        PCR_TRY(c->partials.ensure((size_t)std::max(std::max(blocks, blocksc), cblocks) * kMaxMoments *
-                                       sizeof(double),
-                                   c->device, s));
-        PCR_TRY(c->moments.ensure(kMaxMoments * sizeof(double), c->device, s));
-        PCR_TRY(c->host.ensure(kMaxMoments));
-        size_t esz = c->compute == PCR_F64 ? 8 : 4;
-        if (mode == PCR_GRAD_ADJOINT) {
-            size_t b1 = c->L1.cells() * esz;
-            bool fresh = c->vol1.p == nullptr;
-            PCR_TRY(c->vol1.ensure(b1, c->device, s));
-            if (fresh) HIP_TRY(launch_zero(c->vol1.p, c->vol1.bytes, s));
-            PCR_TRY(c->acc1.ensure((size_t)c->grid.n[0] * c->grid.n[1] * c->grid.n[2] * esz,
-                                   c->device, s));
-            PCR_TRY(c->p.ensure((size_t)M * esz, c->device, s));
-        }
-        return PCR_OK;
-    }
-
-    // One projection of a trial w: moments of (f, h_1..h_K) (fused) or of f
-    // alone with p kept for the adjoint (adjoint).
-    pcr_status eval(const double* w, int mode, Moments& out)
-    {
-        double w_eff[8];
-        effective_w(c->model, w, w_eff);
-        const int K = c->model.K;
-        const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
-        double* mom = (double*)c->moments.p;
-        unsigned* ctr = (unsigned*)c->counter.p;
-        if (mode == PCR_GRAD_FUSED) {
-            {
-                PROF(WARP, s);
-                HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->Lc,
-                                          K, true, c->f0, c->model.mean, c->model.U, w_eff,
-                                          c->volc.p, s));
-            }
-            {
-                PROF(MARCH, s);
-                HIP_TRY(launch_march(c->compute, c->Lc, kc, rgc, msc, c->volc.p, y, nullptr,
-                                     (double*)c->partials.p, mom, ctr, s));
-            }
-        } else {
-            {
-                PROF(WARP, s);
-                HIP_TRY(launch_warp_fused(c->compute, c->model.storage, c->f0_dtype, c->grid, c->L1,
-                                          K, false, c->f0, c->model.mean, c->model.U, w_eff,
-                                          c->vol1.p, s));
-            }
-            {
-                PROF(MARCH, s);
-                HIP_TRY(launch_march(c->compute, c->L1, 1, rg, ms, c->vol1.p, y, c->p.p,
-                                     (double*)c->partials.p, mom, ctr, s));
-            }
-        }
-        int nm = n_moments(kc);
-        HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, nm * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        std::memset(out.m, 0, sizeof out.m);
-        std::memcpy(out.m, c->host.p, nm * sizeof(double));
-        out.M = (double)M;
-        out.K = K;
-        return PCR_OK;
-    }
-
-    // Gradient at the w of the last adjoint eval (its p is in c->p):
-    // g = P^T (2 (p - a y - b)), then sum_v g (df/dx) . u_k.
-    pcr_status grad_adjoint(const double* w, double a, double b, double* grad)
-    {
-        double w_eff[8];
-        effective_w(c->model, w, w_eff);
-        const int K = c->model.K;
-        {
-            PROF(BACKPROJ, s);
-            HIP_TRY(launch_backproject(c->compute, c->grid, rg, nullptr, c->p.p, y, a, b, 2.0,
-                                       c->acc1.p, s));
-        }
-        {
-            PROF(CONTRACT, s);
-            HIP_TRY(launch_contract(c->compute, c->model.storage, c->f0_dtype, c->grid, K, c->f0,
-                                    c->model.mean, c->model.U, w_eff, c->acc1.p,
-                                    (double*)c->partials.p, s));
-        }
-        {
-            PROF(REDUCE, s);
-            HIP_TRY(launch_reduce((const double*)c->partials.p, contract_blocks(c->grid), 8, K,
-                                  (double*)c->moments.p, s));
-        }
-        HIP_TRY(hipMemcpyAsync(c->host.p, c->moments.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int k = 0; k < K; ++k) grad[k] = c->host.p[k];
-        return PCR_OK;
-    }
-
-    // Cost and gradient in w (with the model scales) at (a, b).
-    pcr_status cost_grad_at(const double* w, const Moments& mo, int mode, double a, double b,
-                            double* J, double* grad)
-    {
-        const int K = c->model.K;
-        *J = mo.J(a, b);
-        if (mode == PCR_GRAD_FUSED) {
-            for (int k = 0; k < K; ++k) grad[k] = mo.grad(k, a, b);
-        } else {
-            PCR_TRY(grad_adjoint(w, a, b, grad));
-        }
-        for (int k = 0; k < K; ++k) grad[k] *= c->model.scale ? c->scale[k] : 1.0;
-        return PCR_OK;
-    }
-};
-
-static pcr_status check_opts(const pcr_solve_opts* o, int K)
-{
-    if (!o) return fail(PCR_EINVAL, "opts is NULL");
-    if (o->max_iter < 0 || o->max_backtracks < 1) return fail(PCR_EINVAL, "bad iteration limits");
-    if (!(o->sigma > 0 && o->sigma < 1)) return fail(PCR_EINVAL, "sigma must be in (0, 1)");
-    if (!(o->beta > 0 && o->beta < 1)) return fail(PCR_EINVAL, "beta must be in (0, 1)");
-    if (!(o->eps_g >= 0) || !std::isfinite(o->eps_g)) return fail(PCR_EINVAL, "bad eps_g");
-    if (!(o->fixed_mu >= 0) || !std::isfinite(o->fixed_mu)) return fail(PCR_EINVAL, "bad fixed_mu");
-    if (o->fixed_mu == 0 && !(o->step0 > 0 && std::isfinite(o->step0)))
-        return fail(PCR_EINVAL, "step0 must be > 0");
-    if (o->grad_mode != PCR_GRAD_FUSED && o->grad_mode != PCR_GRAD_ADJOINT)
-        return fail(PCR_EINVAL, "unknown grad_mode %d", o->grad_mode);
-    if (o->localize) {
-        PCR_TRY(check_finite(o->p_ref_mm, 3, "p_ref_mm"));
-        if (!(o->fp_tol_mm > 0) || o->fp_max_iter < 1) return fail(PCR_EINVAL, "bad fixed-point options");
-    }
-    (void)K;
-    return PCR_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -747,6 +650,10 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
     PCR_TRY(check_storage(f0_dtype));
     PCR_TRY(check_compute(compute));
     if (!f0_dev) return fail(PCR_EINVAL, "f0_dev is NULL");
+    const int Cc = channels_for(model->K + 1);
+    if (compute == PCR_F32 &&
+        (double)(grid->n[0] + 3) * (grid->n[1] + 3) * (grid->n[2] + 3) * Cc * 4 >= 2147483648.0)
+        return fail(PCR_EINVAL, "padded multi-channel image exceeds 2 GiB (32-bit offsets)");
     pcr_ctx* c = new (std::nothrow) pcr_ctx();
     if (!c) return fail(PCR_ENOMEM, "host allocation failed");
     c->grid = *grid;
@@ -756,27 +663,7 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
     c->f0_dtype = f0_dtype;
     c->compute = compute;
     c->f0 = f0_dev;
-    pcr_status st = current_device(&c->device);
-    if (st != PCR_OK) {
-        delete c;
-        return st;
-    }
-    c->Lc = make_pad(*grid, channels_for(model->K + 1));
-    c->L1 = make_pad(*grid, 1);
-    size_t esz = compute == PCR_F64 ? 8 : 4;
-    if (compute == PCR_F32 && (double)c->Lc.cells() * c->Lc.C * esz >= 2147483648.0) {
-        delete c;
-        return fail(PCR_EINVAL, "padded multi-channel image exceeds 2 GiB (32-bit offsets)");
-    }
-    st = c->volc.ensure(c->Lc.cells() * c->Lc.C * esz, c->device, nullptr);
-    if (st == PCR_OK) st = c->counter.ensure(256, c->device, nullptr);
-    if (st == PCR_OK) {
-        hipError_t e = launch_zero(c->volc.p, c->volc.bytes, nullptr);
-        if (e == hipSuccess) e = launch_zero(c->counter.p, c->counter.bytes, nullptr);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e != hipSuccess) st = fail(PCR_EDEVICE, "zeroing context scratch: %s", hipGetErrorString(e));
-        c->volc_yfast = 0;
-    }
+    pcr_status st = current_device(&c->sc.device);
     if (st != PCR_OK) {
         delete c;
         return st;
@@ -788,17 +675,12 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
 void pcr_ctx_destroy(pcr_ctx* ctx)
 {
     if (!ctx) return;
-    DeviceGuard dg(ctx->device);
+    DeviceGuard dg(ctx->sc.device);
     (void)hipDeviceSynchronize();
     delete ctx;
 }
 
-size_t pcr_ctx_device_bytes(const pcr_ctx* c)
-{
-    if (!c) return 0;
-    return c->volc.bytes + c->vol1.bytes + c->acc1.bytes + c->p.bytes + c->partials.bytes +
-           c->moments.bytes;
-}
+size_t pcr_ctx_device_bytes(const pcr_ctx* c) { return c ? c->sc.device_bytes() : 0; }
 
 pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
                          const double* w_host, double a, double b, int32_t grad_mode,
@@ -811,13 +693,21 @@ pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
     if (!y_dev || !cost_host || !grad_host) return fail(PCR_EINVAL, "NULL pointer");
     if (grad_mode != PCR_GRAD_FUSED && grad_mode != PCR_GRAD_ADJOINT)
         return fail(PCR_EINVAL, "unknown grad_mode %d", grad_mode);
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->device);
-    Solver S{ctx, (hipStream_t)stream};
-    PCR_TRY(S.prepare(y_dev, *geom, grad_mode));
+    DeviceGuard dg(ctx->sc.device);
+    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->sc.device);
+    Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
+                (hipStream_t)stream};
+    PCR_TRY(E.prepare(y_dev, *geom, grad_mode));
     Moments mo;
-    PCR_TRY(S.eval(w_host, grad_mode, mo));
-    PCR_TRY(S.cost_grad_at(w_host, mo, grad_mode, a, b, cost_host, grad_host));
+    PCR_TRY(E.eval_sync(w_host, mo));
+    *cost_host = mo.J(a, b);
+    const int K = ctx->model.K;
+    if (grad_mode == PCR_GRAD_FUSED) {
+        for (int k = 0; k < K; ++k) grad_host[k] = mo.grad(k, a, b);
+    } else {
+        PCR_TRY(E.grad_adjoint(w_host, a, b, grad_host));
+    }
+    for (int k = 0; k < K; ++k) grad_host[k] *= ctx->scale[k];
     return PCR_OK;
 }
 
@@ -828,83 +718,35 @@ pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev, cons
     if (!ctx) return fail(PCR_EINVAL, "ctx is NULL");
     PCR_TRY(check_geom(geom));
     const int K = ctx->model.K;
-    PCR_TRY(check_opts(opts, K));
+    PCR_TRY(check_opts(opts));
     PCR_TRY(check_finite(w_inout, K, "w_inout"));
     if (!y_dev) return fail(PCR_EINVAL, "y_dev is NULL");
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->device);
-    const int mode = opts->grad_mode;
-    const bool fixed = opts->fixed_mu > 0;
-    Solver S{ctx, (hipStream_t)stream};
-    PCR_TRY(S.prepare(y_dev, *geom, mode));
-
-    double w[8], wt[8], g[8], a, b, J;
-    for (int k = 0; k < K; ++k) w[k] = w_inout[k];
-    Moments mo, mt;
-    PCR_TRY(S.eval(w, mode, mo));
-    mo.step2(&a, &b);
-    PCR_TRY(S.cost_grad_at(w, mo, mode, a, b, &J, g));
-    auto norm = [K](const double* v) {
-        double s = 0;
-        for (int k = 0; k < K; ++k) s += v[k] * v[k];
-        return std::sqrt(s);
-    };
-    double gn = norm(g), g0 = gn, J0 = J;
-    double mu = fixed ? opts->fixed_mu : (g0 > 0 ? opts->step0 / g0 : 0.0);
-    pcr_status status = PCR_OK;
-    int iters = 0, trials = 0;
-    for (int n = 0;; ++n) {
-        if (!std::isfinite(J) || !std::isfinite(gn)) {
-            status = fail(PCR_EDEVICE, "non-finite cost or gradient (input contains NaN/Inf?)");
-            break;
-        }
-        if (gn <= opts->eps_g * g0) break;
-        if (n == opts->max_iter) {
-            status = PCR_ENOCONV;
-            break;
-        }
-        bool accepted = false;
-        for (int l = 0; l < (fixed ? 1 : opts->max_backtracks); ++l) {
-            for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * g[k];
-            PCR_TRY(S.eval(wt, mode, mt));
-            ++trials;
-            if (fixed || mt.J(a, b) <= J - opts->sigma * mu * gn * gn) {
-                accepted = true;
-                break;
-            }
-            mu *= opts->beta;
-        }
-        if (!accepted) {
-            status = PCR_ENOCONV;
-            break;
-        }
-        for (int k = 0; k < K; ++k) w[k] = wt[k];
-        mo = mt;
-        mo.step2(&a, &b);
-        PCR_TRY(S.cost_grad_at(w, mo, mode, a, b, &J, g));
-        gn = norm(g);
-        iters = n + 1;
-        if (!fixed) mu /= opts->beta;
+    DeviceGuard dg(ctx->sc.device);
+    if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->sc.device);
+    Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
+                (hipStream_t)stream};
+    PCR_TRY(E.prepare(y_dev, *geom, opts->grad_mode));
+    SolveSM sm;
+    sm.begin(K, *opts, ctx->model.scale ? ctx->scale : nullptr, w_inout);
+    auto gfn = [&E](const double* w, double a, double b, double* g) { return E.grad_adjoint(w, a, b, g); };
+    while (!sm.done()) {
+        Moments mo;
+        PCR_TRY(E.eval_sync(sm.eval_w(), mo));
+        PCR_TRY(sm.feed(mo, gfn));
     }
-    if (status == PCR_ENOCONV) fail(PCR_ENOCONV, "no convergence: %d iterations, %d trials", iters, trials);
-    for (int k = 0; k < K; ++k) w_inout[k] = w[k];
+    pcr_status status = sm.status;
+    if (status == PCR_EDEVICE) return fail(PCR_EDEVICE, "non-finite cost or gradient (input contains NaN/Inf?)");
+    if (status == PCR_ENOCONV)
+        fail(PCR_ENOCONV, "no convergence: %d iterations, %d trials", sm.iters, sm.trials);
+    for (int k = 0; k < K; ++k) w_inout[k] = sm.w[k];
     if (ab_out) {
-        ab_out[0] = a;
-        ab_out[1] = b;
+        ab_out[0] = sm.a;
+        ab_out[1] = sm.b;
     }
-    pcr_solve_stats st{};
-    st.status = status;
-    st.iterations = iters;
-    st.trials = trials;
-    st.J0 = J0;
-    st.J = J;
-    st.gnorm0 = g0;
-    st.gnorm = gn;
-    st.a = a;
-    st.b = b;
-    st.fp_status = PCR_OK;
-    if (opts->localize && (status == PCR_OK || status == PCR_ENOCONV)) {
-        pcr_status ls = pcr_localize_tumor(&ctx->grid, &ctx->model, w, opts->p_ref_mm, opts->fp_tol_mm,
+    pcr_solve_stats st;
+    sm.fill_stats(&st);
+    if (opts->localize) {
+        pcr_status ls = pcr_localize_tumor(&ctx->grid, &ctx->model, sm.w, opts->p_ref_mm, opts->fp_tol_mm,
                                            opts->fp_max_iter, st.tumor_mm, &st.fp_iterations, stream);
         st.fp_status = ls;
         if (ls != PCR_OK && ls != PCR_EDIVERGE) return ls;

@@ -1,0 +1,293 @@
+// Host-side building blocks shared by the C ABI (api.hip) and the serving
+// engine (serve.hip): error reporting, validation, device scratch, the
+// per-projection evaluator and the resumable solver state machine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+
+#include "pcr.h"
+#include "pcr_internal.h"
+
+namespace pcr {
+
+// ------------------------------------------------------------- errors ----
+// Records a thread-local description (pcr_last_error) and returns `code`.
+pcr_status fail(pcr_status code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::pcr::fail(e_ == hipErrorOutOfMemory ? PCR_ENOMEM : PCR_EDEVICE,         \
+                               "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,    \
+                               __LINE__);                                                    \
+    } while (0)
+
+#define PCR_TRY(expr)                                                                        \
+    do {                                                                                     \
+        pcr_status s_ = (expr);                                                              \
+        if (s_ != PCR_OK) return s_;                                                         \
+    } while (0)
+
+// ----------------------------------------------------------- profiler ----
+namespace prof {
+enum Id { WARP, MARCH, REDUCE, BACKPROJ, CONTRACT, LOCALIZE, ZERO, PAD, UNPAD, COMPOSE, WARP_PLAIN,
+          WARP_ADJ, NKERN };
+// Brackets one launch with HIP events on `s` while profiling is enabled.
+struct Scope {
+    hipStream_t s;
+    int id;
+    hipEvent_t a = nullptr;
+    Scope(int id_, hipStream_t s_);
+    ~Scope();
+};
+}  // namespace prof
+#define PCR_PROF_CAT2(a, b) a##b
+#define PCR_PROF_CAT(a, b) PCR_PROF_CAT2(a, b)
+#define PROF(id, s) ::pcr::prof::Scope PCR_PROF_CAT(prof_scope_, __LINE__)(::pcr::prof::id, s)
+
+// --------------------------------------------------------- validation ----
+size_t dtype_size(pcr_dtype d);
+pcr_status check_grid(const pcr_grid* g);
+pcr_status check_geom(const pcr_geom* G);
+pcr_status check_compute(pcr_dtype d);
+pcr_status check_storage(pcr_dtype d);
+pcr_status check_model(const pcr_model* m);
+pcr_status check_finite(const double* v, int n, const char* what);
+pcr_status check_opts(const pcr_solve_opts* o);
+
+inline void effective_w(const pcr_model& m, const double* w, double* w_eff)
+{
+    for (int k = 0; k < m.K; ++k) w_eff[k] = w[k] * (m.scale ? m.scale[k] : 1.0);
+}
+
+inline int channels_for(int kc) { return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8; }
+
+// Device bytes of a model and reference image stored as given.
+inline size_t model_bytes(const pcr_grid& g, int K, pcr_dtype storage, pcr_dtype f0_dtype)
+{
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    return N * (3 * (size_t)(K + 1) * dtype_size(storage) + dtype_size(f0_dtype));
+}
+
+// ------------------------------------------------------- device scratch --
+// Grow-only device buffer owned by the library.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+    pcr_status ensure(size_t need, int dev, hipStream_t s);
+    void release();
+};
+
+struct HostBuf {
+    double* p = nullptr;
+    size_t n = 0;
+    pcr_status ensure(size_t need);
+    void release();
+};
+
+// Moments of one projection (see n_moments) and the quantities of section
+// 2.2 formed from them.
+struct Moments {
+    double m[kMaxMoments];
+    double M;
+    int K;
+    // J(a, b) = sum (p - a y - b)^2 expanded in the moments (eq. (2))
+    double J(double a, double b) const
+    {
+        return m[4] - 2 * a * m[3] - 2 * b * m[2] + a * a * m[1] + 2 * a * b * m[0] + b * b * M;
+    }
+    // dJ/dw_eff_k = 2 sum (p - a y - b) t_k
+    double grad(int k, double a, double b) const
+    {
+        return 2.0 * (m[5 + 3 * k] - a * m[6 + 3 * k] - b * m[7 + 3 * k]);
+    }
+    // step 2, eq. (4): least-squares (a, b) for Y = [y, 1]; a singular
+    // Y^T Y (constant y) gives a = 0 and b = mean(p)
+    void step2(double* a, double* b) const
+    {
+        double sy = m[0], syy = m[1], sp = m[2], syp = m[3];
+        double D = syy * M - sy * sy;
+        if (!(D > 1e-12 * syy * M)) {
+            *a = 0.0;
+            *b = M > 0 ? sp / M : 0.0;
+            return;
+        }
+        *a = (M * syp - sy * sp) / D;
+        *b = (syy * sp - sy * syp) / D;
+    }
+};
+
+// Device scratch of one solve in flight: the zero-padded fused image, the
+// single-channel image, backprojection and projection buffers of the
+// adjoint mode, reduction partials, moments and pinned host staging.
+struct Scratch {
+    int device = -1;
+    PadLayout Lc{}, L1{};
+    int volc_grid[3] = {0, 0, 0};
+    int volc_yfast = -1;   // layout the zero borders of volc match (-1: none)
+    DevBuf volc, vol1, acc1, p, partials, moments;
+    HostBuf host;
+    void release();
+    size_t device_bytes() const
+    {
+        return volc.bytes + vol1.bytes + acc1.bytes + p.bytes + partials.bytes + moments.bytes;
+    }
+};
+
+// Evaluates projections of trial w for one (grid, model, f0, y, geometry)
+// into one Scratch on one stream.
+struct Evaluator {
+    const pcr_grid* grid;
+    const pcr_model* model;   // scale already applied through effective_w
+    pcr_dtype f0_dtype, compute;
+    const void* f0;
+    Scratch* sc;
+    hipStream_t s;
+    // per projection
+    const void* y = nullptr;
+    RayGeom rg{}, rgc{};
+    MarchShape ms{}, msc{};
+    int M = 0, blocks = 0, blocksc = 0, mode = PCR_GRAD_FUSED;
+
+    pcr_status prepare(const void* y_, const pcr_geom& G, int mode_);
+    // Enqueues warp + march + reduce + copy of the moments to host staging.
+    pcr_status enqueue_eval(const double* w);
+    // After the stream reached the copy: the moments of the last eval.
+    void collect(Moments& out) const;
+    pcr_status eval_sync(const double* w, Moments& out);
+    // Adjoint mode: dJ/dw_eff at the w of the last eval (its p is kept).
+    pcr_status grad_adjoint(const double* w, double a, double b, double* grad);
+};
+
+// The alternating algorithm of section 2.2 as a resumable state machine:
+// the caller evaluates the projection at eval_w() and feeds its moments
+// until done().  The blocking solve and the serving engine drive the same
+// machine, so a solve takes identical steps alone and in a batch.
+struct SolveSM {
+    int K = 0;
+    pcr_solve_opts o{};
+    double scale[8];
+    double w[8], wt[8], g[8];
+    double a = 0, b = 0, J = 0, gn = 0, g0 = 0, J0 = 0, mu = 0;
+    int iters = 0, trials = 0, n = 0, l = 0;
+    enum State { NEED_INIT, NEED_TRIAL, DONE } state = NEED_INIT;
+    pcr_status status = PCR_OK;
+
+    void begin(int K_, const pcr_solve_opts& opts, const double* scale_or_null, const double* w0);
+    const double* eval_w() const { return state == NEED_INIT ? w : wt; }
+    bool done() const { return state == DONE; }
+    // grad_fn (adjoint mode) computes dJ/dw_eff at (w, a, b) from the last
+    // evaluation; null in fused mode (gradient from the moments).
+    template <typename GradFn>
+    pcr_status feed(const Moments& mo, GradFn&& grad_fn);
+    void fill_stats(pcr_solve_stats* st) const;
+
+  private:
+    void advance();
+};
+
+inline void SolveSM::begin(int K_, const pcr_solve_opts& opts, const double* sc, const double* w0)
+{
+    K = K_;
+    o = opts;
+    for (int k = 0; k < 8; ++k) scale[k] = (sc && k < K) ? sc[k] : 1.0;
+    for (int k = 0; k < K; ++k) w[k] = w0[k];
+    iters = trials = n = l = 0;
+    state = NEED_INIT;
+    status = PCR_OK;
+}
+
+template <typename GradFn>
+inline pcr_status SolveSM::feed(const Moments& mo, GradFn&& grad_fn)
+{
+    const bool fixed = o.fixed_mu > 0;
+    auto gradient = [&](const double* wv) -> pcr_status {
+        if (o.grad_mode == PCR_GRAD_FUSED) {
+            for (int k = 0; k < K; ++k) g[k] = mo.grad(k, a, b);
+        } else {
+            pcr_status st = grad_fn(wv, a, b, g);
+            if (st != PCR_OK) return st;
+        }
+        double s2 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            g[k] *= scale[k];
+            s2 += g[k] * g[k];
+        }
+        gn = std::sqrt(s2);
+        return PCR_OK;
+    };
+    if (state == NEED_INIT) {
+        mo.step2(&a, &b);
+        J = mo.J(a, b);
+        PCR_TRY(gradient(w));
+        g0 = gn;
+        J0 = J;
+        mu = fixed ? o.fixed_mu : (g0 > 0 ? o.step0 / g0 : 0.0);
+        advance();
+        return PCR_OK;
+    }
+    if (state != NEED_TRIAL) return PCR_OK;
+    ++trials;
+    if (fixed || mo.J(a, b) <= J - o.sigma * mu * gn * gn) {
+        for (int k = 0; k < K; ++k) w[k] = wt[k];
+        mo.step2(&a, &b);
+        J = mo.J(a, b);
+        PCR_TRY(gradient(w));
+        iters = ++n;
+        if (!fixed) mu /= o.beta;
+        advance();
+        return PCR_OK;
+    }
+    mu *= o.beta;
+    if (++l == o.max_backtracks) {
+        status = PCR_ENOCONV;
+        state = DONE;
+        return PCR_OK;
+    }
+    for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * g[k];
+    return PCR_OK;
+}
+
+inline void SolveSM::advance()
+{
+    if (!std::isfinite(J) || !std::isfinite(gn)) {
+        status = PCR_EDEVICE;
+        state = DONE;
+        return;
+    }
+    if (gn <= o.eps_g * g0) {
+        state = DONE;
+        return;
+    }
+    if (n == o.max_iter) {
+        status = PCR_ENOCONV;
+        state = DONE;
+        return;
+    }
+    l = 0;
+    for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * g[k];
+    state = NEED_TRIAL;
+}
+
+inline void SolveSM::fill_stats(pcr_solve_stats* st) const
+{
+    std::memset(st, 0, sizeof *st);
+    st->status = status;
+    st->iterations = iters;
+    st->trials = trials;
+    st->J0 = J0;
+    st->J = J;
+    st->gnorm0 = g0;
+    st->gnorm = gn;
+    st->a = a;
+    st->b = b;
+    st->fp_status = PCR_OK;
+}
+
+}  // namespace pcr

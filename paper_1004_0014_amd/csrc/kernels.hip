@@ -92,21 +92,21 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
     }
 }
 
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ part, int nblocks,
-                                                int stride, int nm, double* __restrict__ out)
+__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part, int nblocks,
+                                                 int stride, int nm, double* __restrict__ out)
 {
-    // thread (chunk c, moment m): sum of blocks c, c+8, ... then chunks in order
-    __shared__ double chunk[8][32];
+    // thread (chunk c of 32, moment m of 32): sum of blocks c, c+32, ... in
+    // order, then the 32 chunks in order
+    __shared__ double chunk[32][33];
     const int m = threadIdx.x & 31, c = threadIdx.x >> 5;
     double s = 0.0;
     if (m < nm)
-        for (int b = c; b < nblocks; b += 8) s += part[(size_t)b * stride + m];
+        for (int b = c; b < nblocks; b += 32) s += part[(size_t)b * stride + m];
     chunk[c][m] = s;
     __syncthreads();
     if ((int)threadIdx.x < nm) {
         double t = chunk[0][threadIdx.x];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) t += chunk[k][threadIdx.x];
+        for (int k = 1; k < 32; ++k) t += chunk[k][threadIdx.x];
         out[threadIdx.x] = t;
     }
 }
@@ -731,7 +731,12 @@ __global__ void __launch_bounds__(256) k_backproject_brick(RayGeom g, int nbx, i
     const R lo[3] = {(R)(b0x - 1), (R)(b0y - 1), (R)(b0z - 1)};
     const R hi[3] = {(R)(b0x + kBX), (R)(b0y + kBY), (R)(b0z + kBZ)};
     const R fn1[3] = {(R)(nx + 1), (R)(ny + 1), (R)(nz + 1)};
-    for (int rr = threadIdx.x; rr < nr; rr += 256) {
+    // each thread takes a contiguous run of the box's pixels, so that the
+    // 64 lanes of a wave march rays ~nr/256 pixels apart whose samples fall
+    // on different voxels (no same-address LDS atomics within one wave)
+    const int chunk = (nr + 255) / 256;
+    const int r_begin = threadIdx.x * chunk, r_end = min(nr, r_begin + chunk);
+    for (int rr = r_begin; rr < r_end; ++rr) {
         const int iu = iu0 + rr % nub, iv = iv0 + rr / nub;
         const size_t pix = iu + (size_t)g.nu * iv;
         R r = resid ? resid[pix] : (R)(scale * ((double)p[pix] - a * (double)y[pix] - b));
@@ -795,10 +800,11 @@ __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
                                                   const R* __restrict__ gpad,
                                                   double* __restrict__ partials)
 {
-    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
     double m[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) m[kk] = 0.0;
+    for (int k = blockIdx.z; k < g.nz; k += gridDim.z) {
     if (i < g.nx && j < g.ny) {
         size_t N = (size_t)g.nx * g.ny * g.nz;
         size_t v = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * k);
@@ -826,8 +832,9 @@ __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
                 if (kk < K)
-                    m[kk] = gd * (G0 * (double)u[kk][0] + G1 * (double)u[kk][1] + G2 * (double)u[kk][2]);
+                    m[kk] += gd * (G0 * (double)u[kk][0] + G1 * (double)u[kk][1] + G2 * (double)u[kk][2]);
         }
+    }
     }
     // threadIdx is 2-D (64 x 4): flatten for the block reduction
     __shared__ double red[4][8];
@@ -1062,9 +1069,19 @@ int march_blocks(const RayGeom& rg, const MarchShape& ms)
     return tiles_u_of(rg, ms) * ((rg.nv + rows - 1) / rows);
 }
 
-int contract_blocks(const pcr_grid& g)
+// Contraction grid: x-y tiles of 64 x 4 voxels, z split over enough blocks to
+// fill the chip (each block then loops over its z slices).
+static dim3 contract_grid(const pcr_grid& g)
 {
     dim3 d = vox_grid(g);
+    unsigned xy = d.x * d.y;
+    unsigned zb = std::max(1u, std::min((unsigned)g.n[2], (2048u + xy - 1) / xy));
+    return dim3(d.x, d.y, zb);
+}
+
+int contract_blocks(const pcr_grid& g)
+{
+    dim3 d = contract_grid(g);
     return (int)(d.x * d.y * d.z);
 }
 
@@ -1212,7 +1229,7 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     if (moments) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_reduce<<<1, 256, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
+        k_reduce<<<1, 1024, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
     }
     return hipGetLastError();
 }
@@ -1249,7 +1266,7 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
 #undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
-    k_reduce<<<1, 256, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
+    k_reduce<<<1, 1024, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
     return hipGetLastError();
 }
 
@@ -1267,7 +1284,7 @@ hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const Ray
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
                          hipStream_t s)
 {
-    k_reduce<<<1, 256, 0, s>>>(partials, nblocks, stride, nm, out);
+    k_reduce<<<1, 1024, 0, s>>>(partials, nblocks, stride, nm, out);
     return hipGetLastError();
 }
 
@@ -1292,7 +1309,7 @@ hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dt
 {
     auto w = wvec(w_eff, K);
     PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S, PCR_DISPATCH_S(f0_dtype, F,
-        k_contract<R, S, F><<<vox_grid(g), dim3(64, 4), 0, s>>>((const F*)f0, (const S*)mean,
+        k_contract<R, S, F><<<contract_grid(g), dim3(64, 4), 0, s>>>((const F*)f0, (const S*)mean,
                                                                 (const S*)U, K, w, vox(g),
                                                                 (const R*)gv, partials))));
     return hipGetLastError();

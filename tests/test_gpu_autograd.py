@@ -33,7 +33,10 @@ def test_gradcheck_fp64_small():
     f0 = torch.tensor(S.phantom(g), dtype=torch.float64, device=DEV).requires_grad_()
     w = torch.tensor(S.truth_w(m, 1.1) * 0.7, dtype=torch.float64).requires_grad_()
     assert torch.autograd.gradcheck(lambda w_, f_: A.project(w_, f_, g, G, dm), (w, f0),
-                                    eps=1e-6, atol=1e-6, rtol=1e-4)
+                                    eps=1e-6, atol=1e-6, rtol=1e-4,
+                                    # LDS atomics in the backprojection: reruns may differ
+                                    # in the last bits
+                                    nondet_tol=1e-12)
 
 
 @pytest.fixture(scope="module", params=[3, 5])
