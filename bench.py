@@ -121,15 +121,16 @@ class Workload:
         phi = S.breathing_phase(t)
         return angle, t, phi, S.truth_w(self.model, phi)
 
-    def measurements(self, idxs):
+    def measurements(self, idxs, fixed_angle=None):
         """Synthetic measured projections (truth-warped phantom, projected by
-        the library in FP32), kept on the device."""
+        the library in FP32), kept on the device.  With `fixed_angle` (rad)
+        every frame is taken at that gantry angle (fluoroscopy)."""
         import torch
         from paper_1004_0014_amd import synth as S, _lib
         ys, geoms = [], []
         for i in idxs:
             angle, _, _, w = self.frame(i)
-            G = S.geom_for(self.name, angle)
+            G = S.geom_for(self.name, angle if fixed_angle is None else fixed_angle)
             dvf = _lib.dvf_compose(self.grid, self.dmodel, w)
             f = _lib.warp_volume(self.grid, self.f0, dvf)
             ys.append(_lib.forward_project(self.grid, G, f))
@@ -155,19 +156,29 @@ def storage_model(W, storage, dev):
     return _lib.DeviceModel(mean, U, scale=scale), f0
 
 
-def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False):
+def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order=0, hist=None):
+    """Solves the projections in order, each warm-started from the previous
+    result, or with predict_order > 0 from the polynomial extrapolation of
+    the last results to the frame's time (the prediction is inside the timed
+    solve).  `hist` is a list of (t, w) carried across calls."""
     import torch
     from paper_1004_0014_amd import _lib
     lat, iters, trials, werr, terr, evals = [], [], [], [], [], []
     w = list(w0)
+    hist = [] if hist is None else hist
     torch.cuda.synchronize()
     if profile:
         _lib.profile_enable(True)
     t_start = time.perf_counter()
     for n, (y, G, i) in enumerate(zip(ys, geoms, idxs)):
+        t_i = W.frame(i)[1]
         t0 = time.perf_counter()
+        if predict_order > 0 and len(hist) >= 2:
+            last = hist[-(predict_order + 1):]
+            w = _lib.predict_w([h[1] for h in last], [h[0] for h in last], t_i, predict_order)
         w, ab, st = ctx.reconstruct(y, G, w, opts)
         lat.append(time.perf_counter() - t0)
+        hist.append((t_i, list(w)))
         if (n + 1) % 60 == 0:
             log("[bench]   %d solves, last %.2f ms, %d iterations" % (n + 1, 1e3 * lat[-1],
                                                                      st["iterations"]))
@@ -184,7 +195,7 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False):
         _lib.profile_enable(False)
     return dict(lat=np.array(lat), iters=np.array(iters), trials=np.array(trials),
                 evals=np.array(evals), werr=np.array(werr), tumor=np.array(terr), w=w,
-                elapsed=elapsed, prof=prof)
+                elapsed=elapsed, prof=prof, hist=hist)
 
 
 def summarise(res, W, idxs, samples_per_proj):
@@ -284,9 +295,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1")
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
-    ap.add_argument("--variants", default="bf16,adjoint",
+    ap.add_argument("--variants", default="bf16,adjoint,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
     ap.add_argument("--variant-steps", type=int, default=60)
+    ap.add_argument("--predict-order", type=int, default=2,
+                    help="polynomial order of the history predictor in the *predict variants")
+    ap.add_argument("--fluoro-angle", type=float, default=30.0,
+                    help="gantry angle (deg) of the fixed-angle variants")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -339,7 +354,9 @@ def main():
     log("[bench] main line: " + json.dumps(line))
     variants = {}
     vsteps = min(Ks, args.variant_steps)
+    fl = None
     for v in [s for s in args.variants.split(",") if s]:
+        po = 0
         if v in ("bf16", "f16"):
             dm, f0v = storage_model(W, v, dev)
             cv = _lib.Context(W.grid, dm, f0v)
@@ -353,9 +370,27 @@ def main():
             wv = run_sequence(ctx, W, ys[:Wm], geoms[:Wm], idxs[:Wm], o2, [0.0] * K)
             rv = run_sequence(ctx, W, ys[Wm:Wm + vsteps], geoms[Wm:Wm + vsteps],
                               idxs[Wm:Wm + vsteps], o2, wv["w"], profile=True)
+        elif v in ("predict", "fluoro", "fluoro-predict"):
+            po = args.predict_order if v.endswith("predict") else 0
+            if v.startswith("fluoro"):
+                if fl is None:
+                    fl = W.measurements(idxs[:Wm + vsteps], fixed_angle=math.radians(args.fluoro_angle))
+                vy, vg = fl
+            else:
+                vy, vg = ys, geoms
+            wv = run_sequence(ctx, W, vy[:Wm], vg[:Wm], idxs[:Wm], opts, [0.0] * K,
+                              predict_order=po)
+            rv = run_sequence(ctx, W, vy[Wm:Wm + vsteps], vg[Wm:Wm + vsteps],
+                              idxs[Wm:Wm + vsteps], opts, wv["w"], profile=True,
+                              predict_order=po, hist=wv["hist"])
+            vspp = np.array([float(samples_per_ray(W.grid, G).sum()) for G in vg[Wm:Wm + vsteps]])
         else:
             continue
-        sv = summarise(rv, W, idxs[Wm:Wm + vsteps], spp[Wm:Wm + vsteps])
+        sv = summarise(rv, W, idxs[Wm:Wm + vsteps], vspp if v.startswith("fluoro") else spp[Wm:Wm + vsteps])
+        if v.startswith("fluoro"):
+            sv["angle_deg"] = args.fluoro_angle
+        if po:
+            sv["predict_order"] = po
         sv["steps"] = vsteps
         sv["kernels"] = kernel_table(rv["prof"])
         variants[v] = sv

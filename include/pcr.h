@@ -116,7 +116,9 @@ typedef struct pcr_solve_opts {
     double beta;             /* step shrink per rejected trial (0.5) */
     double eps_g;            /* stop when |g_n| <= eps_g |g_0| (1e-4) */
     double step0;            /* first trial of a solve moves w by this distance (> 0);
-                                later iterations start from the last accepted step / beta */
+                                a later iteration's first trial is the minimiser of the
+                                quadratic through the previous line's J, slope -|g|^2 and
+                                accepted J', clamped to [beta, 1/beta] x the accepted step */
     double fixed_mu;         /* > 0: constant step mu, no line search (default 0) */
     int32_t grad_mode;       /* PCR_GRAD_FUSED (default) or PCR_GRAD_ADJOINT */
     int32_t localize;        /* nonzero: localise the tumour after the solve */
@@ -226,6 +228,29 @@ pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev,
                                            double* w_inout, double* ab_out,
                                            pcr_solve_stats* stats, void* stream);
 
+/* PCA training of the motion model (section 2.1, eq. (1); section 3): from J
+ * training DVFs dvfs_dev [J][3][N] (FP32, mm), writes mean_dev [3][N] =
+ * their average and U_dev [K][3][N] = the K leading left singular vectors of
+ * the centred 3N x J matrix (unit norm; each flipped so that its first entry
+ * within 1e-5 relative of its largest magnitude is positive), and on the host
+ * sing_host[K] (singular values) and w_train_host [J][K] (training
+ * coefficients <U_k, d_j - mean>), either may be NULL.  2 <= J <= 16,
+ * 1 <= K <= min(8, J - 1).  The Gram matrix accumulates in FP64; the
+ * eigen-solve is FP64 on the host.  Synchronises `stream`. */
+pcr_status pcr_pca_train(const pcr_grid* grid, int32_t J, const float* dvfs_dev, int32_t K,
+                         float* mean_dev, float* U_dev, double* sing_host, double* w_train_host,
+                         void* stream);
+
+/* Initial guess from history (section 5: the PCA coefficients predicted from
+ * previous frames serve as the initial guess, useful when the imaging rate is
+ * low).  w_hist [n][K] are previous results at times t_hist [n] (seconds,
+ * strictly increasing); w_out[K] = the polynomial of degree
+ * min(order, n - 1) through the last min(order, n - 1) + 1 points, evaluated
+ * at t_next (order 0: the last result, the plain warm start; 1: linear
+ * extrapolation; 2: quadratic).  Host only; no device work. */
+pcr_status pcr_predict_w(const double* w_hist, const double* t_hist, int32_t n, int32_t K,
+                         double t_next, int32_t order, double* w_out);
+
 /* Tumour localisation (section 2.3): the point p with p + x(p) = p_ref for
  * the pull-back DVF x = mean + U (scale * w), by the fixed-point iteration
  * p <- p_ref - x(p) (Chen et al., the paper's ref. 13) evaluated at that
@@ -258,6 +283,9 @@ typedef struct pcr_server_opts {
     int32_t max_slots;        /* solves in flight at once (1..64) */
     int32_t drop_stale;       /* nonzero: a queued (not yet started) request is dropped
                                  when a newer one of the same stream arrives */
+    int32_t predict_order;    /* warm start of each solve: 0 = the stream's previous
+                                 result; 1, 2 = pcr_predict_w over the stream's last
+                                 results at their submit times */
 } pcr_server_opts;
 
 typedef struct pcr_result {

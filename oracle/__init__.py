@@ -282,3 +282,27 @@ def localize(grid, mean, U, w, p_ref, tol=1e-6, max_iter=200):
     st = _load().orc_localize(C.byref(_grid(grid)), K, _p(mean), _p(U), _p(w), _p(p_ref),
                               tol, max_iter, _p(out), C.byref(it))
     return out, st, it.value
+
+
+def pca(dvfs, K):
+    """PCA of the motion model (section 2.1, eq. (1); section 3): dvfs
+    [J][3][...] training DVFs.  mean = their average; U = the K leading left
+    singular vectors of the centred 3N x J matrix (numpy SVD, float64), each
+    flipped so that its first entry within 1e-5 (relative) of its largest
+    magnitude is positive; w_train[j][k] = <U_k, d_j - mean>.  Returns
+    (mean, U, singular values, w_train)."""
+    d = np.asarray(dvfs, dtype=np.float64)
+    J = d.shape[0]
+    X = d.reshape(J, -1).T                       # 3N x J
+    mean = X.mean(axis=1)
+    Xc = X - mean[:, None]
+    u, s, _ = np.linalg.svd(Xc, full_matrices=False)
+    U = u[:, :K].copy()
+    for k in range(K):
+        a = np.abs(U[:, k])
+        j = int(np.flatnonzero(a >= (1 - 1e-5) * a.max())[0])
+        if U[j, k] < 0:
+            U[:, k] = -U[:, k]
+    w_train = Xc.T @ U
+    shape = d.shape[1:]
+    return mean.reshape(shape), U.T.reshape((K,) + shape), s[:K], w_train

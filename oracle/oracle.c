@@ -428,13 +428,28 @@ static double norm(int K, const double* v)
     return sqrt(s);
 }
 
+/* First trial step of the next iteration from the line just searched:
+ * phi(mu) = J - g2 mu + c mu^2 through phi(mu_acc) = Jt has its minimum at
+ * g2 / (2 c); the result is kept within one backtracking factor of mu_acc. */
+static double next_initial_step(double J, double g2, double Jt, double mu_acc, double beta)
+{
+    double c = (Jt - J + mu_acc * g2) / (mu_acc * mu_acc);
+    double m = c > 0.0 ? g2 / (2.0 * c) : mu_acc / beta;
+    if (m < beta * mu_acc) m = beta * mu_acc;
+    if (m > mu_acc / beta) m = mu_acc / beta;
+    return m;
+}
+
 /* The alternating algorithm of section 2.2.  Readings where the paper is
  * silent: (a, b) start with step 2 at w_0; step 1 is gradient descent on w
  * with a, b fixed and the step from Armijo's rule: trial w - mu g accepted
  * when J' <= J - sigma mu |g|^2 (ties accept), otherwise mu <- beta mu for at
- * most max_backtracks trials; the first trial of a solve moves w by step0,
- * each later iteration starts from the last accepted mu divided by beta; step
- * 2 then refits (a, b) at the accepted w.  Stop when |g_n| <= eps_g |g_0|, or
+ * most max_backtracks trials; the first trial of a solve moves w by step0;
+ * each later iteration's first trial is the minimiser of the quadratic in mu
+ * that matches the previous iteration's line (its J, its slope -|g|^2 and the
+ * accepted trial's J'), kept within [beta mu', mu'/beta] of the accepted mu'
+ * (mu'/beta where that quadratic has no minimum); step 2 then refits (a, b)
+ * at the accepted w.  Stop when |g_n| <= eps_g |g_0|, or
  * at the iteration cap, or when the line search is exhausted (the last
  * accepted w is kept).  J_hist, if given, receives J after each step 2. */
 int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
@@ -460,6 +475,7 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
         if (gn <= o->eps_g * g0) break;
         if (n == o->max_iter) { status = ORC_ENOCONV; break; }
         int accepted = 0;
+        double Jt = 0.0;
         if (o->fixed_mu > 0) {
             for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * grad[k];
             forward_at(g, G, f0, K, mean, U, wt, p);
@@ -470,12 +486,13 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
                 for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * grad[k];
                 forward_at(g, G, f0, K, mean, U, wt, p);
                 ++trials;
-                double Jt = orc_cost(M, p, y, ab[0], ab[1], NULL);
+                Jt = orc_cost(M, p, y, ab[0], ab[1], NULL);
                 if (Jt <= J - o->sigma * mu * gn * gn) { accepted = 1; break; }
                 mu *= o->beta;
             }
         }
         if (!accepted) { status = ORC_ENOCONV; break; }
+        double J_line = J, g2_line = gn * gn;
         for (int k = 0; k < K; ++k) w[k] = wt[k];
         orc_regression_sums(M, y, p, S);
         orc_step2(S, ab);
@@ -483,7 +500,7 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
         gn = norm(K, grad);
         iters = n + 1;
         if (J_hist) J_hist[iters] = J;
-        if (!(o->fixed_mu > 0)) mu /= o->beta;
+        if (!(o->fixed_mu > 0)) mu = next_initial_step(J_line, g2_line, Jt, mu, o->beta);
     }
     if (st) {
         st->iterations = iters; st->trials = trials; st->status = status;

@@ -64,7 +64,8 @@ class SolveStats(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32),
+                ("predict_order", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -128,6 +129,8 @@ def lib():
             "pcr_server_get_w": (C.c_int32, [_P, C.c_int32, _PD]),
             "pcr_server_set_w": (C.c_int32, [_P, C.c_int32, _PD]),
             "pcr_server_device_bytes": (C.c_size_t, [_P]),
+            "pcr_predict_w": (C.c_int32, [_PD, _PD, C.c_int32, C.c_int32, C.c_double, C.c_int32, _PD]),
+            "pcr_pca_train": (C.c_int32, [G, C.c_int32, _P, C.c_int32, _P, _P, _PD, _PD, _P]),
             "pcr_profile_enable": (None, [C.c_int32]),
             "pcr_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_char_p), _PD,
                                              C.POINTER(C.c_int64)]),
@@ -265,6 +268,31 @@ def warp_contract(grid, model: DeviceModel, f0: torch.Tensor, w, gvol: torch.Ten
     return [out[k] for k in range(model.K)]
 
 
+def pca_train(grid, dvfs: torch.Tensor, K: int, stream=None):
+    """GPU PCA of J training DVFs [J][3][nz][ny][nx] (FP32): returns (mean,
+    U, singular values, w_train [J][K])."""
+    import numpy as np
+    g = make_grid(grid)
+    J = int(dvfs.shape[0])
+    mean = torch.empty(dvfs.shape[1:], dtype=torch.float32, device=dvfs.device)
+    U = torch.empty((K,) + tuple(dvfs.shape[1:]), dtype=torch.float32, device=dvfs.device)
+    sing = (C.c_double * K)()
+    wt = (C.c_double * (J * K))()
+    _check(lib().pcr_pca_train(C.byref(g), J, _ptr(dvfs), K, _ptr(mean), _ptr(U), sing, wt,
+                               _stream(stream)))
+    return mean, U, np.array(list(sing)), np.array(list(wt)).reshape(J, K)
+
+
+def predict_w(w_hist, t_hist, t_next, order=1):
+    """Initial guess extrapolated from previous results (host only)."""
+    import numpy as np
+    wh = np.ascontiguousarray(w_hist, dtype=np.float64)
+    n, K = wh.shape
+    out = (C.c_double * K)()
+    _check(lib().pcr_predict_w(_dd(wh.ravel()), _dd(t_hist), n, K, float(t_next), int(order), out))
+    return list(out)
+
+
 def localize_tumor(grid, model: DeviceModel, w, p_ref, tol=1e-6, max_iter=200, stream=None):
     """Returns (position mm [3], status, iterations)."""
     g = make_grid(grid)
@@ -357,8 +385,9 @@ class Server:
     solves for many streams.  Streams' reference images and models are copied
     into server-owned device memory at add_stream."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True):
-        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0)
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True,
+                 predict_order: int = 0):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0, int(predict_order))
         h = C.c_void_p()
         _check(lib().pcr_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpcr.so")
-SOURCES = ["kernels.hip", "api.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "api.hip", "serve.hip", "pca.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

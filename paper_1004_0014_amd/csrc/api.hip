@@ -595,6 +595,29 @@ pcr_status pcr_warp_contract(const pcr_grid* grid, const pcr_model* model, pcr_d
     return PCR_OK;
 }
 
+pcr_status pcr_predict_w(const double* w_hist, const double* t_hist, int32_t n, int32_t K,
+                         double t_next, int32_t order, double* w_out)
+{
+    if (!w_hist || !t_hist || !w_out) return fail(PCR_EINVAL, "NULL argument");
+    if (n < 1 || K < 1 || K > 8 || order < 0 || order > 2) return fail(PCR_EINVAL, "bad n, K or order");
+    PCR_TRY(check_finite(w_hist, n * K, "w_hist"));
+    PCR_TRY(check_finite(t_hist, n, "t_hist"));
+    if (!std::isfinite(t_next)) return fail(PCR_EINVAL, "t_next must be finite");
+    const int d = std::min(order, n - 1);
+    const int first = n - 1 - d;
+    for (int i = first + 1; i < n; ++i)
+        if (!(t_hist[i] > t_hist[i - 1])) return fail(PCR_EINVAL, "t_hist must increase");
+    // Lagrange form of the interpolating polynomial through points first..n-1
+    for (int k = 0; k < K; ++k) w_out[k] = 0.0;
+    for (int i = first; i < n; ++i) {
+        double L = 1.0;
+        for (int j = first; j < n; ++j)
+            if (j != i) L *= (t_next - t_hist[j]) / (t_hist[i] - t_hist[j]);
+        for (int k = 0; k < K; ++k) w_out[k] += L * w_hist[i * K + k];
+    }
+    return PCR_OK;
+}
+
 pcr_status pcr_localize_tumor(const pcr_grid* grid, const pcr_model* model, const double* w_host,
                               const double p_ref_mm[3], double tol_mm, int32_t max_iter,
                               double p_out_mm[3], int32_t* iters, void* stream)

@@ -169,6 +169,19 @@ struct Evaluator {
 // the caller evaluates the projection at eval_w() and feeds its moments
 // until done().  The blocking solve and the serving engine drive the same
 // machine, so a solve takes identical steps alone and in a batch.
+// Armijo's rule (section 2.2) with a per-iteration first trial: the
+// minimiser of the quadratic phi(mu) = J - g2 mu + c mu^2 that passes through
+// the accepted trial phi(mu_acc) = Jt of the line just searched, kept within
+// [beta mu_acc, mu_acc / beta] (mu_acc / beta when c <= 0).
+inline double next_initial_step(double J, double g2, double Jt, double mu_acc, double beta)
+{
+    const double c = (Jt - J + mu_acc * g2) / (mu_acc * mu_acc);
+    double m = c > 0.0 ? g2 / (2.0 * c) : mu_acc / beta;
+    if (m < beta * mu_acc) m = beta * mu_acc;
+    if (m > mu_acc / beta) m = mu_acc / beta;
+    return m;
+}
+
 struct SolveSM {
     int K = 0;
     pcr_solve_opts o{};
@@ -234,13 +247,15 @@ inline pcr_status SolveSM::feed(const Moments& mo, GradFn&& grad_fn)
     }
     if (state != NEED_TRIAL) return PCR_OK;
     ++trials;
-    if (fixed || mo.J(a, b) <= J - o.sigma * mu * gn * gn) {
+    const double Jt = mo.J(a, b);
+    if (fixed || Jt <= J - o.sigma * mu * gn * gn) {
+        const double J_line = J, g2_line = gn * gn;
         for (int k = 0; k < K; ++k) w[k] = wt[k];
         mo.step2(&a, &b);
         J = mo.J(a, b);
         PCR_TRY(gradient(w));
         iters = ++n;
-        if (!fixed) mu /= o.beta;
+        if (!fixed) mu = next_initial_step(J_line, g2_line, Jt, mu, o.beta);
         advance();
         return PCR_OK;
     }

@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstdlib>
 #include <utility>
@@ -532,6 +533,7 @@ struct MarchArgs {
     int tiles_u;
     const void* vol;       // padded image, C float channels per cell
     unsigned vol_bytes;
+    int px, py, pz;        // padded dims in memory order (cells)
     int ys, zs;            // byte strides of the padded y and z axes
     float fn1[3];          // clamp bound n_a + 1 (padded index space)
     int kc;                // channels used
@@ -1052,7 +1054,7 @@ MarchShape choose_march_shape(const RayGeom& rg)
         int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4) ms.seg = v;
     }
-    ms.buffer_loads = true;
+    ms.buffer_loads = false;
     if (const char* e = std::getenv("PCR_MARCH_GLOBAL")) ms.buffer_loads = std::atoi(e) == 0;
     if (ms.tile_u > 256 / ms.seg) ms.tile_u = 256 / ms.seg;
     return ms;
@@ -1244,6 +1246,9 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.tiles_u = tiles_u_of(rg, ms);
     A.vol = padded;
     A.vol_bytes = (unsigned)(L.cells() * (size_t)L.C * 4);
+    A.px = L.px;
+    A.py = L.py;
+    A.pz = L.pz;
     A.ys = L.px * L.C * 4;
     A.zs = L.px * L.py * L.C * 4;
     for (int a = 0; a < 3; ++a) A.fn1[a] = (float)(rg.lim[a] + 1.0);

@@ -41,6 +41,10 @@ struct Stream {
     DevBuf f0, mean, U;
     pcr_solve_opts opts{};
     double w[8];
+    // last results and their submit times (history for the predicted warm start)
+    double hist_w[3][8];
+    double hist_t[3];
+    int nhist = 0;
     bool active = false;
     bool removing = false;
     size_t bytes = 0;
@@ -124,6 +128,17 @@ bool pcr_server::start_slot(Slot& sl)
     sl.E = Evaluator{&st->grid, &st->model, st->f0_dtype, PCR_F32, st->f0.p, &sl.sc, sl.s};
     sl.t_start = now_s();
     for (int k = 0; k < 8; ++k) sl.w0[k] = k < st->model.K ? st->w[k] : 0.0;
+    if (o.predict_order > 0 && st->nhist >= 2) {
+        double wh[3 * 8], th[3];
+        const int K = st->model.K;
+        for (int i = 0; i < st->nhist; ++i) {
+            th[i] = st->hist_t[i];
+            for (int k = 0; k < K; ++k) wh[i * K + k] = st->hist_w[i][k];
+        }
+        double wp[8];
+        if (pcr_predict_w(wh, th, st->nhist, K, sl.req.t_submit, o.predict_order, wp) == PCR_OK)
+            for (int k = 0; k < K; ++k) sl.w0[k] = wp[k];
+    }
     pcr_status e = sl.E.prepare(sl.req.y, sl.req.geom, PCR_GRAD_FUSED);
     if (e == PCR_OK) {
         sl.sm.begin(st->model.K, st->opts, st->model.scale ? st->scale : nullptr, sl.w0);
@@ -165,8 +180,19 @@ void pcr_server::finish_slot(Slot& sl, pcr_status err)
     }
     res.t_done_s = now_s();
     std::lock_guard<std::mutex> lk(mu);
-    if (err == PCR_OK && (res.status == PCR_OK || res.status == PCR_ENOCONV))
+    if (err == PCR_OK && (res.status == PCR_OK || res.status == PCR_ENOCONV)) {
         for (int k = 0; k < st->model.K; ++k) st->w[k] = res.w[k];
+        if (st->nhist == 3) {
+            for (int i = 0; i < 2; ++i) {
+                st->hist_t[i] = st->hist_t[i + 1];
+                for (int k = 0; k < 8; ++k) st->hist_w[i][k] = st->hist_w[i + 1][k];
+            }
+            st->nhist = 2;
+        }
+        st->hist_t[st->nhist] = sl.req.t_submit;
+        for (int k = 0; k < 8; ++k) st->hist_w[st->nhist][k] = res.w[k];
+        ++st->nhist;
+    }
     st->active = false;
     sl.busy = false;
     sl.pending = false;
@@ -254,6 +280,7 @@ pcr_status pcr_server_create(const pcr_server_opts* opts, pcr_server** out)
     if (!opts || !out) return fail(PCR_EINVAL, "NULL argument");
     *out = nullptr;
     if (opts->max_slots < 1 || opts->max_slots > 64) return fail(PCR_EINVAL, "max_slots must be in 1..64");
+    if (opts->predict_order < 0 || opts->predict_order > 2) return fail(PCR_EINVAL, "predict_order must be 0..2");
     if (opts->hbm_budget_bytes == 0) return fail(PCR_EINVAL, "hbm_budget_bytes must be > 0");
     auto S = std::make_unique<pcr_server>();
     S->o = *opts;
@@ -470,6 +497,7 @@ pcr_status pcr_server_set_w(pcr_server* S, int32_t sid, const double* w)
     PCR_TRY(check_finite(w, it->second->model.K, "w"));
     if (it->second->active) return fail(PCR_EBUSY, "stream %d has a solve in flight", sid);
     for (int k = 0; k < it->second->model.K; ++k) it->second->w[k] = w[k];
+    it->second->nhist = 0;
     return PCR_OK;
 }
 

@@ -1,0 +1,64 @@
+"""Kernel-profiling driver: repeats one pass of the hot path at the
+paper-scale workload (256x256x100 volume, K = 3, 512x384 detector) so that
+`rocprofv3` can time it or read its counters, and runs a plain device copy of
+a known size beside it to calibrate the byte counters.
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1004_0014_amd.kprof
+    rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python3 -m paper_1004_0014_amd.kprof
+
+Each repetition is one fused cost-and-gradient evaluation (warp + march +
+reduce) at a fixed gantry angle, or one backprojection with --what backproject.
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import sys
+
+import torch
+
+from . import _lib, synth as S
+
+COPY_BYTES = 256 << 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--angle", type=float, default=30.0)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    g = S.grid_for(args.config)
+    K = S.CONFIGS[args.config]["K"]
+    G = S.geom_for(args.config, math.radians(args.angle))
+    m = S.pca_model(g, K)
+    dt = torch.float32 if args.storage == "f32" else torch.bfloat16
+    f0 = torch.tensor(S.phantom(g), dtype=torch.float32, device=dev)
+    dm32 = _lib.DeviceModel(torch.tensor(m.mean, dtype=torch.float32, device=dev),
+                            torch.tensor(m.U, dtype=torch.float32, device=dev))
+    w = S.truth_w(m, 2.0)
+    y = _lib.forward_project(g, G, _lib.warp_volume(g, f0, _lib.dvf_compose(g, dm32, w)))
+    dm = dm32 if dt == torch.float32 else _lib.DeviceModel(dm32.mean.to(dt), dm32.U.to(dt))
+    f0s = f0.to(dt)
+    ctx = _lib.Context(g, dm, f0s)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        if args.what in ("fused", "adjoint"):
+            ctx.cost_grad(y, G, 0.9 * w, 1.0, 0.0, mode=0 if args.what == "fused" else 1)
+        elif args.what == "backproject":
+            _lib.backproject_residual(g, G, y)
+        else:
+            _lib.forward_project(g, G, f0)
+        dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written
+    torch.cuda.synchronize()
+    print("kprof done: %s x%d at %s, %s storage" % (args.what, args.reps, args.config, args.storage),
+          file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

@@ -229,10 +229,11 @@ class PCAModel:
 
 
 def _sign_index(u):
-    """Index of the first entry (storage order) whose magnitude is within 1e-9
-    of the largest; symmetric motion patterns have several such entries."""
+    """Index of the first entry (storage order) whose magnitude is within 1e-5
+    (relative) of the largest; symmetric motion patterns have several such
+    entries, and the tolerance sits well above FP32 rounding."""
     a = np.abs(u)
-    return int(np.flatnonzero(a >= (1 - 1e-9) * a.max())[0])
+    return int(np.flatnonzero(a >= (1 - 1e-5) * a.max())[0])
 
 
 def pca_model(grid: Grid, K: int, R: int | None = None, n_phases: int = 10,
@@ -241,7 +242,7 @@ def pca_model(grid: Grid, K: int, R: int | None = None, n_phases: int = 10,
     phases 2 pi j / n_phases, j = 1..n_phases-1 (j = 0 is the end-of-exhale
     reference with x = 0), mean = their average, U = the K leading left
     singular vectors of the centred 3N x (n_phases-1) matrix, each flipped so
-    that its largest-magnitude entry (the first, within 1e-9) is positive.
+    that its largest-magnitude entry (the first, within 1e-5) is positive.
 
     Because every training DVF is X = P C (patterns P, coefficients C), the
     SVD is taken exactly through the R x R pattern Gram matrix Q = P^T P:

@@ -59,3 +59,23 @@ def test_oracle_and_product_are_independent():
     for p, txt in _imports(os.path.join(ROOT, "paper_1004_0014_amd")):
         assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, re.M), p
         assert "oracle.h" not in txt, p
+
+
+def test_predict_w_is_polynomial_extrapolation():
+    """pcr_predict_w (host-only): exact on sequences of the polynomial degree
+    it uses; order 0 is the plain warm start."""
+    import numpy as np
+    from paper_1004_0014_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpcr.so not built")
+    t = np.array([0.0, 0.09, 0.2, 0.27])
+    a, b, c = np.array([1.0, -2.0, 0.5]), np.array([3.0, 0.25, -1.0]), np.array([-0.7, 2.0, 4.0])
+    lin = np.stack([a + b * ti for ti in t])
+    quad = np.stack([a + b * ti + c * ti * ti for ti in t])
+    tn = 0.36
+    np.testing.assert_allclose(_lib.predict_w(lin, t, tn, 1), a + b * tn, rtol=1e-12)
+    np.testing.assert_allclose(_lib.predict_w(quad, t, tn, 2), a + b * tn + c * tn * tn, rtol=1e-12)
+    np.testing.assert_array_equal(_lib.predict_w(quad, t, tn, 0), quad[-1])
+    np.testing.assert_array_equal(_lib.predict_w(quad[:1], t[:1], tn, 2), quad[0])
+    with pytest.raises(_lib.PCRError):
+        _lib.predict_w(quad, t[::-1], tn, 1)          # times must increase

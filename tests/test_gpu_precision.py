@@ -1,0 +1,101 @@
+"""16-bit storage of the reference image and eigenvector fields (precision
+configuration: K = 4, BF16 and FP16, FP16 fields stored divided by their
+largest magnitude; FP32 ray accumulation, FP64 detector-wide reductions and
+w step).  Errors are stated against the FP32 path and the FP64 oracle:
+
+* kernel error: the 16-bit path against the oracle fed the same rounded
+  values (FP32-level agreement, <= 1e-5);
+* storage error: against the oracle on the unrounded FP64 inputs
+  (target <= 1e-2 relative projection error);
+* solves: recovered w against the FP32 path's, tumour position within 0.1 mm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1004_0014_amd import synth as S
+from helpers import rel_l2, rounded
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _L():
+    from paper_1004_0014_amd import _lib
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def case():
+    # the precision configuration's shape at reduced size (a quarter of the
+    # voxels per axis, a quarter of the detector), same spacing family
+    g = S.Grid((96, 96, 48), (5.0, 5.0, 6.67))
+    K = 4
+    m = S.pca_model(g, K)
+    f0 = S.phantom(g)
+    G = S.Geom(math.radians(58.0), 192, 144, 2.07, 2.07, 2.5)
+    return dict(g=g, K=K, m=m, f0=f0, G=G)
+
+
+def _model(case, storage):
+    L = _L()
+    m = case["m"]
+    if storage == "f16":
+        scale = np.abs(m.U.reshape(case["K"], -1)).max(axis=1)
+        U_t, U = rounded(m.U / scale[:, None, None, None, None], torch.float16)
+        U = U * scale[:, None, None, None, None]
+    else:
+        scale = None
+        U_t, U = rounded(m.U, {"bf16": torch.bfloat16, "f32": torch.float32}[storage])
+    dt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}[storage]
+    mean_t, mean = rounded(m.mean, dt)
+    f0_t, f0 = rounded(case["f0"], dt)
+    dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV), scale=scale)
+    return dm, f0_t.to(DEV), dict(mean=mean, U=U, f0=f0)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_projection_error_16bit(case, storage):
+    L = _L()
+    g, G, m = case["g"], case["G"], case["m"]
+    dm, f0d, r = _model(case, storage)
+    w = S.truth_w(m, 2.3)
+    # warped projection through the library (compose + warp + project)
+    dvf = L.dvf_compose(g, dm, w)
+    p = L.forward_project(g, G, L.warp_volume(g, f0d, dvf)).cpu().double().numpy()
+    # kernel error: oracle on the same rounded inputs
+    po_r = oracle.project(g, G, oracle.warp(g, r["f0"], oracle.compose(g, r["mean"], r["U"], w)))
+    assert rel_l2(p, po_r) <= 1e-5
+    # storage error: oracle on the FP64 inputs
+    po = oracle.project(g, G, oracle.warp(g, case["f0"], oracle.compose(g, m.mean, m.U, w)))
+    err = rel_l2(p, po)
+    assert err <= 1e-2, err
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_solve_and_tumour_16bit(case, storage):
+    L = _L()
+    g, G, m = case["g"], case["G"], case["m"]
+    w_true = S.truth_w(m, 1.9)
+    # measured projection of the exact (FP64) deformed phantom
+    y_np = oracle.project(g, G, oracle.warp(g, case["f0"], oracle.compose(g, m.mean, m.U, w_true)))
+    y = torch.tensor(y_np, dtype=torch.float32, device=DEV)
+    p_ref = S.tumor_center(g)
+    opts = L.default_opts(max_iter=120, step0=m.step0, eps_g=1e-6, localize=1, p_ref_mm=p_ref)
+    res = {}
+    for st in ("f32", storage):
+        dm, f0d, _ = _model(case, st)
+        ctx = L.Context(g, dm, f0d)
+        res[st] = ctx.reconstruct(y, G, np.zeros(case["K"]), opts)
+        ctx.close()
+    w32, _, s32 = res["f32"]
+    w16, _, s16 = res[storage]
+    pt, _, _ = oracle.localize(g, m.mean, m.U, w_true, p_ref, tol=1e-9)
+    # tumour position: against the FP32 path and against the truth
+    assert np.linalg.norm(np.array(s16["tumor_mm"]) - np.array(s32["tumor_mm"])) <= 0.1
+    assert np.linalg.norm(np.array(s16["tumor_mm"]) - pt) <= 0.1
+    # leading coefficients agree with the FP32 path to the storage precision
+    assert abs(w16[0] - w32[0]) <= 1e-2 * abs(w32[0])

@@ -159,3 +159,26 @@ def test_stale_frame_dropped_and_state_restore(streams):
     with pytest.raises(L.PCRError):
         srv.submit(sa, a.ys[0], a.geoms[0])
     srv.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_predicted_warm_start(streams, order):
+    """With predict_order > 0 a stream's next solve starts from the polynomial
+    extrapolation of its last results to the new frame's submit time."""
+    L = _L()
+    st = streams[1]
+    srv = L.Server(hbm_budget_bytes=4 << 30, max_slots=1, predict_order=order)
+    sid = srv.add_stream(st.grid, st.dm, st.df0, st.opts, np.zeros(st.K))
+    res = []
+    for j in range(3):
+        srv.submit(sid, st.ys[j], st.geoms[j])
+        srv.drain()
+        res += srv.poll(4)
+    assert [r["status"] in (0, -4) for r in res] == [True] * 3
+    # frame 1 has one result of history: plain warm start
+    assert res[1]["w0"] == res[0]["w"]
+    hist = res[:2]
+    expect = L.predict_w([r["w"] for r in hist], [r["t_submit_s"] for r in hist],
+                         res[2]["t_submit_s"], order)
+    assert np.allclose(res[2]["w0"], expect, rtol=1e-12, atol=1e-12)
+    srv.close()

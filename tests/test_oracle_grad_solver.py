@@ -150,6 +150,50 @@ def test_fixed_step_mode_is_plain_gradient_descent(small):
     assert st["iterations"] == 2 and st["trials"] == 2
 
 
+def test_line_search_on_exact_quadratic_is_block_coordinate_descent():
+    """A reference image linear in z, warped by one mode that vanishes near the
+    grid faces, is reproduced exactly by trilinear interpolation, so P f is
+    affine in w and J(w, a, b) is an exact quadratic.  Along a line it is then
+    exactly phi(mu) = J - |g|^2 mu + c mu^2, so from the second iteration on
+    the first Armijo trial is the exact line minimiser 1 / (2 |P h|^2): no
+    trial is rejected and the iterates are those of block-coordinate descent
+    (exact minimisation in w, then in (a, b)), computed here from p(0) and
+    q = p(1) - p(0) alone."""
+    g = S.Grid((20, 18, 22), (5.0, 5.0, 5.0))
+    nz, ny, nx = g.shape
+    k = np.arange(nz)[:, None, None] * np.ones((nz, ny, nx))
+    f0 = 0.01 + 0.002 * k
+    bump = lambda n: np.where((np.arange(n) >= 3) & (np.arange(n) <= n - 4),
+                              np.sin(np.pi * (np.arange(n) - 3) / (n - 7)) ** 2, 0.0)
+    U = np.zeros((1, 3) + g.shape)
+    U[0, 2] = 4.0 * bump(nz)[:, None, None] * bump(ny)[None, :, None] * bump(nx)[None, None, :]
+    mean = np.zeros((3,) + g.shape)
+    geom = S.Geom(0.4, nu=40, nv=36, du=4.0, dv=4.0, step=2.5)
+    proj = lambda w: oracle.project(g, geom, oracle.warp(g, f0, oracle.compose(g, mean, U, [w])))
+    p0 = proj(0.0)
+    q = proj(1.0) - p0
+    y = (proj(0.37) - 0.002) / 1.7
+    Y = np.stack([y.ravel(), np.ones(y.size)], axis=1)
+    ab_of = lambda w: np.linalg.lstsq(Y, (p0 + w * q).ravel(), rcond=None)[0]
+    qq = float(np.sum(q * q))
+    mu_star = 1.0 / (2.0 * qq)
+    a, b = ab_of(0.0)
+    g0 = 2.0 * float(np.sum(q * (p0 - a * y - b)))
+    # model iterates: a 0.7 mu* first step, then exact line minimisation
+    ws, w = [], 0.0
+    for n in range(5):
+        grad = 2.0 * float(np.sum(q * (p0 + w * q - a * y - b)))
+        w = w - (0.7 if n == 0 else 1.0) * mu_star * grad
+        a, b = ab_of(w)
+        ws.append((w, a, b))
+    for N in (1, 2, 3, 5):
+        opts = oracle.SolveOpts(max_iter=N, step0=0.7 * mu_star * abs(g0), eps_g=0.0)
+        w, (a, b), st, _ = oracle.solve(g, geom, f0, mean, U, y, [0.0], opts)
+        assert st["iterations"] == N and st["trials"] == N
+        np.testing.assert_allclose([w[0], a, b], ws[N - 1], rtol=1e-7, atol=1e-12)
+    assert abs(ws[-1][0] - 0.37) < 1e-3
+
+
 def test_localize_constant_dvf():
     g = S.Grid((10, 10, 10), (2.0, 2.0, 2.0))
     c = np.array([1.5, -2.0, 3.25])
