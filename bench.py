@@ -163,7 +163,7 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
     solve).  `hist` is a list of (t, w) carried across calls."""
     import torch
     from paper_1004_0014_amd import _lib
-    lat, iters, trials, werr, terr, evals = [], [], [], [], [], []
+    lat, iters, trials, werr, terr, evals, samples = [], [], [], [], [], [], []
     w = list(w0)
     hist = [] if hist is None else hist
     torch.cuda.synchronize()
@@ -185,6 +185,7 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
         iters.append(st["iterations"])
         trials.append(st["trials"])
         evals.append(st["trials"] + 1)
+        samples.append(st["samples"])
         _, _, phi, wt = W.frame(i)
         werr.append(float(np.linalg.norm(np.array(w) - wt) / np.linalg.norm(wt)))
         terr.append(st["tumor_mm"])
@@ -194,7 +195,8 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
     if profile:
         _lib.profile_enable(False)
     return dict(lat=np.array(lat), iters=np.array(iters), trials=np.array(trials),
-                evals=np.array(evals), werr=np.array(werr), tumor=np.array(terr), w=w,
+                evals=np.array(evals), samples=np.array(samples), werr=np.array(werr),
+                tumor=np.array(terr), w=w,
                 elapsed=elapsed, prof=prof, hist=hist)
 
 
@@ -204,7 +206,10 @@ def summarise(res, W, idxs, samples_per_proj):
     for i, p in zip(idxs, res["tumor"]):
         _, _, phi, _ = W.frame(i)
         tumour_err.append(float(np.linalg.norm(p - true_tumour(W.grid, phi, W.K, 1.5, W.p_ref))))
+    # samples of the definition (every ray over the whole support box) and
+    # samples actually marched (rays clipped to where the image can be nonzero)
     samples = float(np.sum(res["evals"] * samples_per_proj))
+    marched = float(np.sum(res["samples"]))
     return {
         "solves_per_s": len(lat) / res["elapsed"],
         "p50_ms": float(np.percentile(lat, 50)),
@@ -212,7 +217,9 @@ def summarise(res, W, idxs, samples_per_proj):
         "mean_ms": float(lat.mean()),
         "mean_iterations": float(res["iters"].mean()),
         "mean_trials": float(res["trials"].mean()),
-        "ray_samples_per_s": samples / res["elapsed"],
+        "ray_samples_per_s": marched / res["elapsed"],
+        "ray_samples_per_s_support_box": samples / res["elapsed"],
+        "marched_fraction": marched / samples,
         "w_rel_err_vs_truth_median": float(np.median(res["werr"])),
         "w_rel_err_vs_truth_max": float(np.max(res["werr"])),
         "tumour_err_mm_mean": float(np.mean(tumour_err)),
@@ -297,7 +304,9 @@ def main():
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
     ap.add_argument("--variants", default="bf16,adjoint,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
-    ap.add_argument("--variant-steps", type=int, default=60)
+    ap.add_argument("--variant-steps", type=int, default=0,
+                    help="steps of each variant (0: as many as the main run; the adjoint "
+                         "variant at most 60)")
     ap.add_argument("--predict-order", type=int, default=2,
                     help="polynomial order of the history predictor in the *predict variants")
     ap.add_argument("--fluoro-angle", type=float, default=30.0,
@@ -347,16 +356,17 @@ def main():
                                           "tumour_err_mm_mean", "tumour_err_mm_max",
                                           "mean_iterations", "mean_trials")},
         "kernels": kernel_table(res["prof"]),
-        "roofline": roofline(W, res["prof"], float(spp[Wm:].mean()), channels),
+        "roofline": roofline(W, res["prof"],
+                             float(np.sum(res["samples"])) / max(res["prof"]["march"][1], 1), channels),
     }
     log("[bench] main: %.1f solves/s p50 %.2f ms p99 %.2f ms" % (summ["solves_per_s"], summ["p50_ms"],
                                                                  summ["p99_ms"]))
     log("[bench] main line: " + json.dumps(line))
     variants = {}
-    vsteps = min(Ks, args.variant_steps)
     fl = None
     for v in [s for s in args.variants.split(",") if s]:
         po = 0
+        vsteps = min(Ks, args.variant_steps or (60 if v == "adjoint" else Ks))
         if v in ("bf16", "f16"):
             dm, f0v = storage_model(W, v, dev)
             cv = _lib.Context(W.grid, dm, f0v)
@@ -383,7 +393,8 @@ def main():
             rv = run_sequence(ctx, W, vy[Wm:Wm + vsteps], vg[Wm:Wm + vsteps],
                               idxs[Wm:Wm + vsteps], opts, wv["w"], profile=True,
                               predict_order=po, hist=wv["hist"])
-            vspp = np.array([float(samples_per_ray(W.grid, G).sum()) for G in vg[Wm:Wm + vsteps]])
+            if v.startswith("fluoro"):
+                vspp = np.full(vsteps, float(samples_per_ray(W.grid, vg[Wm]).sum()))
         else:
             continue
         sv = summarise(rv, W, idxs[Wm:Wm + vsteps], vspp if v.startswith("fluoro") else spp[Wm:Wm + vsteps])

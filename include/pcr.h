@@ -137,6 +137,9 @@ typedef struct pcr_solve_stats {
     double gnorm0, gnorm;    /* |dJ/dw| at the start and at the result */
     double a, b;             /* intensity fit at the result */
     double tumor_mm[3];      /* localised tumour position (if requested) */
+    double samples;          /* ray samples marched over all projections of the solve
+                                (rays are clipped to the box where the warped image
+                                can be nonzero, so this is the work done) */
 } pcr_solve_stats;
 
 typedef struct pcr_ctx pcr_ctx;

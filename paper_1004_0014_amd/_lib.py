@@ -55,7 +55,8 @@ class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("trials", C.c_int32),
                 ("fp_iterations", C.c_int32), ("fp_status", C.c_int32), ("J0", C.c_double),
                 ("J", C.c_double), ("gnorm0", C.c_double), ("gnorm", C.c_double),
-                ("a", C.c_double), ("b", C.c_double), ("tumor_mm", C.c_double * 3)]
+                ("a", C.c_double), ("b", C.c_double), ("tumor_mm", C.c_double * 3),
+                ("samples", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -271,22 +271,29 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     const int Cc = channels_for(model->K + 1);
     const size_t esz = dtype_size(compute);
     sc->Lc = make_pad(*grid, Cc, yfast);
+    // 16-bit storage of the model: the fused image in FP16 too (half the
+    // bytes per tap for the march), FP32 arithmetic and FP64 moments
+    if (compute == PCR_F32 && (model->storage == PCR_BF16 || model->storage == PCR_F16) && sup &&
+        sup->valid) {
+        sc->Lc.half = true;
+        half_scales(*sup, *grid, model->K, sc->Lc.hs);
+    }
     sc->L1 = make_pad(*grid, 1);
     rgc = make_ray_geom(*grid, G, yfast);
     msc = choose_march_shape(rgc);
     blocksc = march_blocks(rgc, msc);
     const int dev = sc->device;
     if (mode == PCR_GRAD_FUSED) {
-        bool fresh = sc->volc.p == nullptr || sc->volc.bytes < sc->Lc.cells() * Cc * esz;
-        PCR_TRY(sc->volc.ensure(sc->Lc.cells() * Cc * esz, dev, s));
-        bool same_grid = sc->volc_grid[0] == grid->n[0] && sc->volc_grid[1] == grid->n[1] &&
-                         sc->volc_grid[2] == grid->n[2];
-        if (fresh || !same_grid || sc->volc_yfast != (int)yfast) {
-            // border cells of one layout (or grid) are interior cells of another
+        const size_t need = sc->Lc.cells() * sc->Lc.cell_bytes(esz);
+        bool fresh = sc->volc.p == nullptr || sc->volc.bytes < need;
+        PCR_TRY(sc->volc.ensure(need, dev, s));
+        if (fresh || !sc->volc_zeroed || !sc->volc_layout.same_storage(sc->Lc)) {
+            // border cells of one layout (grid, channel count, element
+            // type, axis order) are interior cells of another
             PROF(ZERO, s);
             HIP_TRY(launch_zero(sc->volc.p, sc->volc.bytes, s));
-            sc->volc_yfast = (int)yfast;
-            for (int a = 0; a < 3; ++a) sc->volc_grid[a] = grid->n[a];
+            sc->volc_layout = sc->Lc;
+            sc->volc_zeroed = true;
         }
     } else {
         size_t b1 = sc->L1.cells() * esz;
@@ -308,6 +315,77 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     return PCR_OK;
 }
 
+pcr_status compute_support(const pcr_grid& g, const pcr_model& m, pcr_dtype f0_dtype,
+                           const void* f0, int device, hipStream_t s, Support* out)
+{
+    const int rows = 3 + 3 * m.K;   // then one more: max |f0|
+    DevBuf d;
+    PCR_TRY(d.ensure(64 + (rows + 1) * sizeof(float), device, s));
+    int box[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+    float mx[28] = {0};
+    float* dmx = (float*)((char*)d.p + 64);
+    HIP_TRY(hipMemcpyAsync(d.p, box, sizeof box, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dmx, mx, (rows + 1) * sizeof(float), hipMemcpyHostToDevice, s));
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    HIP_TRY(launch_support(f0_dtype, g, f0, (int*)d.p, s));
+    HIP_TRY(launch_absmax_rows(m.storage, m.mean, N, 3, dmx, s));
+    HIP_TRY(launch_absmax_rows(m.storage, m.U, N, 3 * m.K, dmx + 3, s));
+    HIP_TRY(launch_absmax_rows(f0_dtype, f0, N, 1, dmx + rows, s));
+    HIP_TRY(hipMemcpyAsync(box, d.p, sizeof box, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(mx, dmx, (rows + 1) * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int a = 0; a < 3; ++a) {
+        out->lo[a] = box[a];
+        out->hi[a] = box[3 + a];
+        out->mmax[a] = mx[a];
+        for (int k = 0; k < 8; ++k) out->umax[k][a] = k < m.K ? mx[3 + 3 * k + a] : 0.0;
+    }
+    out->f0max = mx[rows];
+    out->valid = true;
+    return PCR_OK;
+}
+
+void half_scales(const Support& sp, const pcr_grid& g, int K, float hs[8])
+{
+    auto pow2_for = [](double bound) {
+        // largest power of two with bound * scale <= 2^14 (FP16 max 65504)
+        if (!(bound > 0.0) || !std::isfinite(bound)) return 1.0f;
+        int e = (int)std::floor(std::log2(16384.0 / bound));
+        e = std::max(-100, std::min(100, e));
+        return (float)std::ldexp(1.0, e);
+    };
+    for (int c = 0; c < 8; ++c) hs[c] = 1.0f;
+    hs[0] = pow2_for(sp.f0max);
+    for (int k = 0; k < K && k < 7; ++k) {
+        double b = 0.0;
+        for (int a = 0; a < 3; ++a) b += sp.umax[k][a] / g.spacing_mm[a];
+        hs[k + 1] = pow2_for(2.0 * sp.f0max * b);
+    }
+}
+
+void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
+              double clo[3], double chi[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (sp.lo[a] > sp.hi[a]) {   // f0 is zero: so is every projection
+            clo[0] = clo[1] = clo[2] = chi[0] = chi[1] = chi[2] = -1.0;
+            return;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        double d = sp.mmax[a];
+        for (int k = 0; k < K; ++k) d += std::fabs(w_eff[k]) * sp.umax[k][a];
+        // in voxels, with room for the FP32 rounding of the displacements
+        d = d * 1.0001 / g.spacing_mm[a];
+        clo[a] = std::max(-1.0, (double)sp.lo[a] - d - 2.5);
+        chi[a] = std::min((double)g.n[a], (double)sp.hi[a] + d + 2.5);
+    }
+    if (swap_xy) {
+        std::swap(clo[0], clo[1]);
+        std::swap(chi[0], chi[1]);
+    }
+}
+
 pcr_status Evaluator::enqueue_eval(const double* w)
 {
     double w_eff[8];
@@ -315,6 +393,11 @@ pcr_status Evaluator::enqueue_eval(const double* w)
     const int K = model->K;
     const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
     double* mom = (double*)sc->moments.p;
+    RayGeom gc = rgc, g1 = rg;
+    if (sup && sup->valid) {
+        clip_box(*sup, *grid, K, w_eff, sc->Lc.yfast, gc.clo, gc.chi);
+        clip_box(*sup, *grid, K, w_eff, false, g1.clo, g1.chi);
+    }
     if (mode == PCR_GRAD_FUSED) {
         {
             PROF(WARP, s);
@@ -323,7 +406,7 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         }
         {
             PROF(MARCH, s);
-            HIP_TRY(launch_march(compute, sc->Lc, kc, rgc, msc, sc->volc.p, y, nullptr,
+            HIP_TRY(launch_march(compute, sc->Lc, kc, gc, msc, sc->volc.p, y, nullptr,
                                  (double*)sc->partials.p, mom, nullptr, s));
         }
     } else {
@@ -334,11 +417,12 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         }
         {
             PROF(MARCH, s);
-            HIP_TRY(launch_march(compute, sc->L1, 1, rg, ms, sc->vol1.p, y, sc->p.p,
+            HIP_TRY(launch_march(compute, sc->L1, 1, g1, ms, sc->vol1.p, y, sc->p.p,
                                  (double*)sc->partials.p, mom, nullptr, s));
         }
     }
-    HIP_TRY(hipMemcpyAsync(sc->host.p, mom, n_moments(kc) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sc->host.p, mom, (n_moments(kc) + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
     return PCR_OK;
 }
 
@@ -347,6 +431,7 @@ void Evaluator::collect(Moments& out) const
     const int kc = mode == PCR_GRAD_FUSED ? model->K + 1 : 1;
     std::memset(out.m, 0, sizeof out.m);
     std::memcpy(out.m, sc->host.p, n_moments(kc) * sizeof(double));
+    out.samples = sc->host.p[n_moments(kc)];
     out.M = (double)M;
     out.K = model->K;
 }
@@ -658,6 +743,7 @@ struct pcr_ctx {
     pcr_dtype f0_dtype, compute;
     const void* f0;
     Scratch sc;
+    Support sup;   // computed on the first evaluation
     ~pcr_ctx() { sc.release(); }
 };
 
@@ -718,8 +804,12 @@ pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
         return fail(PCR_EINVAL, "unknown grad_mode %d", grad_mode);
     DeviceGuard dg(ctx->sc.device);
     if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->sc.device);
+    if (!ctx->sup.valid)
+        PCR_TRY(compute_support(ctx->grid, ctx->model, ctx->f0_dtype, ctx->f0, ctx->sc.device,
+                                (hipStream_t)stream, &ctx->sup));
     Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
                 (hipStream_t)stream};
+    E.sup = &ctx->sup;
     PCR_TRY(E.prepare(y_dev, *geom, grad_mode));
     Moments mo;
     PCR_TRY(E.eval_sync(w_host, mo));
@@ -746,8 +836,12 @@ pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev, cons
     if (!y_dev) return fail(PCR_EINVAL, "y_dev is NULL");
     DeviceGuard dg(ctx->sc.device);
     if (!dg.ok) return fail(PCR_EDEVICE, "cannot select device %d", ctx->sc.device);
+    if (!ctx->sup.valid)
+        PCR_TRY(compute_support(ctx->grid, ctx->model, ctx->f0_dtype, ctx->f0, ctx->sc.device,
+                                (hipStream_t)stream, &ctx->sup));
     Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
                 (hipStream_t)stream};
+    E.sup = &ctx->sup;
     PCR_TRY(E.prepare(y_dev, *geom, opts->grad_mode));
     SolveSM sm;
     sm.begin(K, *opts, ctx->model.scale ? ctx->scale : nullptr, w_inout);

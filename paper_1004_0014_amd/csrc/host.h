@@ -96,6 +96,7 @@ struct HostBuf {
 struct Moments {
     double m[kMaxMoments];
     double M;
+    double samples = 0;   // ray samples marched
     int K;
     // J(a, b) = sum (p - a y - b)^2 expanded in the moments (eq. (2))
     double J(double a, double b) const
@@ -129,8 +130,8 @@ struct Moments {
 struct Scratch {
     int device = -1;
     PadLayout Lc{}, L1{};
-    int volc_grid[3] = {0, 0, 0};
-    int volc_yfast = -1;   // layout the zero borders of volc match (-1: none)
+    PadLayout volc_layout{};   // layout whose zero borders volc holds
+    bool volc_zeroed = false;
     DevBuf volc, vol1, acc1, p, partials, moments;
     HostBuf host;
     void release();
@@ -142,6 +143,30 @@ struct Scratch {
 
 // Evaluates projections of trial w for one (grid, model, f0, y, geometry)
 // into one Scratch on one stream.
+// Where the warped image can be nonzero.  f0 is zero outside the index box
+// [lo, hi] of its nonzero voxels, and a displacement moves values by at most
+// max|mean_a| + sum_k |w_k| max|U_k,a| along axis a, so the warped channels
+// (f and the tangents, which use the same eight taps) vanish outside that
+// box dilated by the displacement and one cell, and a ray sample contributes
+// nothing outside it dilated by one more cell.  The march clips rays to this
+// box: the samples it skips are exactly zero, the sample grid is unchanged.
+struct Support {
+    bool valid = false;
+    int lo[3], hi[3];        // nonzero f0 voxels (lo > hi: none)
+    double mmax[3];          // max |mean_a| (mm)
+    double umax[8][3];       // max |U_k,a| of the stored fields
+    double f0max;            // max |f0|
+};
+// FP16 channel scales (powers of two): f is bounded by max|f0| and h_k by
+// 2 max|f0| sum_a max|U_k,a| / s_a (each partial derivative of the
+// interpolant is a weighted difference of neighbouring values).
+void half_scales(const Support& sp, const pcr_grid& g, int K, float hs[8]);
+pcr_status compute_support(const pcr_grid& g, const pcr_model& m, pcr_dtype f0_dtype,
+                           const void* f0, int device, hipStream_t s, Support* out);
+// Ray clip box (index space; x and y swapped for the y-fastest layout).
+void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
+              double clo[3], double chi[3]);
+
 struct Evaluator {
     const pcr_grid* grid;
     const pcr_model* model;   // scale already applied through effective_w
@@ -149,6 +174,7 @@ struct Evaluator {
     const void* f0;
     Scratch* sc;
     hipStream_t s;
+    const Support* sup = nullptr;   // null: rays span the whole support box
     // per projection
     const void* y = nullptr;
     RayGeom rg{}, rgc{};
@@ -187,7 +213,7 @@ struct SolveSM {
     pcr_solve_opts o{};
     double scale[8];
     double w[8], wt[8], g[8];
-    double a = 0, b = 0, J = 0, gn = 0, g0 = 0, J0 = 0, mu = 0;
+    double a = 0, b = 0, J = 0, gn = 0, g0 = 0, J0 = 0, mu = 0, samples = 0;
     int iters = 0, trials = 0, n = 0, l = 0;
     enum State { NEED_INIT, NEED_TRIAL, DONE } state = NEED_INIT;
     pcr_status status = PCR_OK;
@@ -212,6 +238,7 @@ inline void SolveSM::begin(int K_, const pcr_solve_opts& opts, const double* sc,
     for (int k = 0; k < 8; ++k) scale[k] = (sc && k < K) ? sc[k] : 1.0;
     for (int k = 0; k < K; ++k) w[k] = w0[k];
     iters = trials = n = l = 0;
+    samples = 0;
     state = NEED_INIT;
     status = PCR_OK;
 }
@@ -220,6 +247,7 @@ template <typename GradFn>
 inline pcr_status SolveSM::feed(const Moments& mo, GradFn&& grad_fn)
 {
     const bool fixed = o.fixed_mu > 0;
+    samples += mo.samples;
     auto gradient = [&](const double* wv) -> pcr_status {
         if (o.grad_mode == PCR_GRAD_FUSED) {
             for (int k = 0; k < K; ++k) g[k] = mo.grad(k, a, b);
@@ -302,6 +330,7 @@ inline void SolveSM::fill_stats(pcr_solve_stats* st) const
     st->gnorm = gn;
     st->a = a;
     st->b = b;
+    st->samples = samples;
     st->fp_status = PCR_OK;
 }
 

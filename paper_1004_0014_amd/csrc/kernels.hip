@@ -23,6 +23,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstdlib>
+#include <type_traits>
 #include <utility>
 
 #include "pcr_internal.h"
@@ -93,19 +94,23 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
     }
 }
 
+// out[0..nm) = sums of slots 0..nm-1 over the blocks' records; with
+// extra >= 0 also out[nm] = the sum of slot `extra`.
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part, int nblocks,
-                                                 int stride, int nm, double* __restrict__ out)
+                                                 int stride, int nm, int extra,
+                                                 double* __restrict__ out)
 {
     // thread (chunk c of 32, moment m of 32): sum of blocks c, c+32, ... in
     // order, then the 32 chunks in order
     __shared__ double chunk[32][33];
     const int m = threadIdx.x & 31, c = threadIdx.x >> 5;
+    const int slot = m < nm ? m : (m == nm ? extra : -1);
     double s = 0.0;
-    if (m < nm)
-        for (int b = c; b < nblocks; b += 32) s += part[(size_t)b * stride + m];
+    if (slot >= 0)
+        for (int b = c; b < nblocks; b += 32) s += part[(size_t)b * stride + slot];
     chunk[c][m] = s;
     __syncthreads();
-    if ((int)threadIdx.x < nm) {
+    if ((int)threadIdx.x < nm + (extra >= 0 ? 1 : 0)) {
         double t = chunk[0][threadIdx.x];
         for (int k = 1; k < 32; ++k) t += chunk[k][threadIdx.x];
         out[threadIdx.x] = t;
@@ -232,36 +237,56 @@ __device__ __forceinline__ Chan<R, C> warp_cell(const F* __restrict__ f0, const 
     return o;
 }
 
+// Cell as stored: the compute type, or (H) FP16 of value * hs[c].
+template <typename R, int C, bool H>
+using CellOf = Chan<typename std::conditional<H, _Float16, R>::type, C>;
+template <typename R, int C, bool H>
+__device__ __forceinline__ CellOf<R, C, H> store_cell(const Chan<R, C>& o, const Chan<float, 8>& hs)
+{
+    if constexpr (!H) {
+        return o;
+    } else {
+        CellOf<R, C, H> h;
+#pragma unroll
+        for (int c = 0; c < C; ++c) h.v[c] = (_Float16)((float)o.v[c] * hs.v[c]);
+        return h;
+    }
+}
+
 // x-fastest padded layout: block 64 (x) x 4 (y), coalesced in x both ways.
-template <typename R, typename S, typename F, int C, bool TAN>
+template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
                                                     const S* __restrict__ mean,
                                                     const S* __restrict__ U, int K,
                                                     Chan<double, 8> w, VoxGrid g, int px, int py,
-                                                    Chan<R, C>* __restrict__ out)
+                                                    Chan<float, 8> hs,
+                                                    CellOf<R, C, H>* __restrict__ out)
 {
     int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
     if (i >= g.nx || j >= g.ny) return;
     Chan<R, C> o = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
-    out[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))] = o;
+    out[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))] =
+        store_cell<R, C, H>(o, hs);
 }
 
 // y-fastest padded layout: a 32 x 32 (x, y) tile per block, computed with
 // x-contiguous reads, staged in LDS and written as 32-cell runs along y.
-template <typename R, typename S, typename F, int C, bool TAN>
+template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        const S* __restrict__ mean,
                                                        const S* __restrict__ U, int K,
                                                        Chan<double, 8> w, VoxGrid g, int px,
-                                                       int py, Chan<R, C>* __restrict__ out)
+                                                       int py, Chan<float, 8> hs,
+                                                       CellOf<R, C, H>* __restrict__ out)
 {
-    __shared__ Chan<R, C> tile[32][33];
+    __shared__ CellOf<R, C, H> tile[32][33];
     const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = i0 + tx, j = j0 + ty + 8 * r;
-        if (i < g.nx && j < g.ny) tile[ty + 8 * r][tx] = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
+        if (i < g.nx && j < g.ny)
+            tile[ty + 8 * r][tx] = store_cell<R, C, H>(warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k), hs);
     }
     __syncthreads();
 #pragma unroll
@@ -336,10 +361,10 @@ __device__ __forceinline__ RaySeg<R> ray_segment(const RayGeom& g, int iu, int i
     for (int a = 0; a < 3; ++a) {
         dq[a] = D[a] / L;
         if (dq[a] != 0.0) {
-            double t1 = (-1.0 - g.qs[a]) / dq[a], t2 = (g.lim[a] - g.qs[a]) / dq[a];
+            double t1 = (g.clo[a] - g.qs[a]) / dq[a], t2 = (g.chi[a] - g.qs[a]) / dq[a];
             tmin = fmax(tmin, fmin(t1, t2));
             tmax = fmin(tmax, fmax(t1, t2));
-        } else if (!(g.qs[a] > -1.0 && g.qs[a] < g.lim[a])) {
+        } else if (!(g.qs[a] > g.clo[a] && g.qs[a] < g.chi[a])) {
             hit = false;
         }
     }
@@ -392,8 +417,10 @@ __global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int til
     R acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = (R)0;
+    int nsamp = 0;
     if (valid) {
         RaySeg<R> rs = ray_segment<R>(g, iu, iv, ms.seg, sid);
+        nsamp = rs.count;
         const long pxy = (long)px * py;
         const Chan<R, C>* base = vol + (1 + px + pxy);   // cell of voxel (0,0,0)
         for (int m = 0; m < rs.count; ++m) {
@@ -436,10 +463,12 @@ __global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int til
     const R dt = (R)g.dt;
     if (owner && p_out) p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
     if (partials) {
+        // record per block: the moments, then the number of samples marched
         constexpr int NM = 5 + 3 * (C - 1);
-        double m[NM];
+        double m[NM + 1];
 #pragma unroll
         for (int i = 0; i < NM; ++i) m[i] = 0.0;
+        m[NM] = (double)nsamp;
         if (owner) {
             double yd = (double)y[iu + (size_t)g.nu * iv];
             double pd = (double)(dt * acc[0]);
@@ -458,7 +487,7 @@ __global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int til
                 }
             }
         }
-        block_sum_store<NM>(m, 5 + 3 * (kc - 1), partials + (size_t)blockIdx.x * NM);
+        block_sum_store<NM + 1>(m, NM + 1, partials + (size_t)blockIdx.x * (NM + 1));
     }
 }
 
@@ -527,6 +556,37 @@ __device__ __forceinline__ CellPair<C> load_pair(__amdgpu_buffer_rsrc_t r, int v
     return p;
 }
 
+// Same pair from FP16 cells (values as stored: times the channel scale).
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+template <int C>
+__device__ __forceinline__ CellPair<C> load_pair_h(const char* base, int off)
+{
+    CellPair<C> p;
+    if constexpr (C == 2) {
+        h4v v;
+        __builtin_memcpy(&v, base + off, sizeof v);
+        p.a[0] = (float)v[0];
+        p.a[1] = (float)v[1];
+        p.b[0] = (float)v[2];
+        p.b[1] = (float)v[3];
+    } else {
+#pragma unroll
+        for (int h = 0; h < C / 4; ++h) {
+            // cells x and x+1 are adjacent: 2 C halves, read 8 at a time
+            h8v v;
+            __builtin_memcpy(&v, base + off + 16 * h, sizeof v);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int idx = 8 * h + e;       // half index within the pair
+                if (idx < C) p.a[idx] = (float)v[e];
+                else p.b[idx - C] = (float)v[e];
+            }
+        }
+    }
+    return p;
+}
+
 struct MarchArgs {
     RayGeom g;
     MarchShape ms;
@@ -542,11 +602,14 @@ struct MarchArgs {
     double* partials;      // [blocks][NM] or null
     double* moments;       // final moments (last block) or null
     unsigned* counter;     // last-block counter
+    float ihs[8];          // FP16 cells: 1 / channel scale
 };
 
-template <int C, bool BUF>
+template <int C, bool BUF, bool H>
 __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
 {
+    static_assert(!(H && BUF), "FP16 cells use global loads");
+    constexpr int CB = (H ? 2 : 4) * C;   // bytes per cell
     const RayGeom& g = A.g;
     const int rpb = 256 / A.ms.seg;
     const int rloc = threadIdx.x % rpb, sid = threadIdx.x / rpb;
@@ -559,8 +622,10 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    int nsamp = 0;
     if (valid) {
         RaySeg<float> rs = ray_segment<float>(g, iu, iv, A.ms.seg, sid);
+        nsamp = rs.count;
         // padded index space: cell i+1 holds voxel i, so q + 1 >= 0 after the
         // clamp and truncation is the floor
         const float q0x = rs.q0[0] + 1.f, q0y = rs.q0[1] + 1.f, q0z = rs.q0[2] + 1.f;
@@ -575,9 +640,15 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
             const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
             const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
                         az = __builtin_amdgcn_fractf(qz);
-            const int voff = ix * (4 * C) + __umul24(iy, YS) + __umul24(iz, ZS);
+            const int voff = ix * CB + __umul24(iy, YS) + __umul24(iz, ZS);
             CellPair<C> p00, p10, p01, p11;
-            if constexpr (BUF) {
+            if constexpr (H) {
+                const char* vb = (const char*)A.vol;
+                p00 = load_pair_h<C>(vb, voff);
+                p10 = load_pair_h<C>(vb, voff + YS);
+                p01 = load_pair_h<C>(vb, voff + ZS);
+                p11 = load_pair_h<C>(vb, voff + YZ);
+            } else if constexpr (BUF) {
                 p00 = load_pair<C>(rsrc, voff, 0);
                 p10 = load_pair<C>(rsrc, voff, YS);
                 p01 = load_pair<C>(rsrc, voff, ZS);
@@ -618,14 +689,20 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
 #pragma unroll
                 for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
     }
+    if constexpr (H) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] *= A.ihs[c];   // exact: powers of two
+    }
     const bool owner = valid && sid == 0;
     const float dt = (float)g.dt;
     if (owner && A.p_out) A.p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
     if (A.partials) {
+        // record per block: the moments, then the number of samples marched
         constexpr int NM = 5 + 3 * (C - 1);
-        double mo[NM];
+        double mo[NM + 1];
 #pragma unroll
         for (int i = 0; i < NM; ++i) mo[i] = 0.0;
+        mo[NM] = (double)nsamp;
         if (owner) {
             double yd = (double)A.y[iu + (size_t)g.nu * iv];
             double pd = (double)(dt * acc[0]);
@@ -644,152 +721,248 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
                 }
             }
         }
-        const int nm = 5 + 3 * (A.kc - 1);
-        block_sum_store<NM>(mo, nm, A.partials + (size_t)blockIdx.x * NM);
+        block_sum_store<NM + 1>(mo, NM + 1, A.partials + (size_t)blockIdx.x * (NM + 1));
     }
 }
 
-// --------------------------------------------------- brick backprojection
-// P^T r without global atomics: one workgroup owns a BX x BY x BZ brick of the
-// output held in LDS.  A sample at index-space point q feeds voxel v iff
-// floor(q_a) is v_a - 1 or v_a on every axis, i.e. q lies in the box
-// [b0 - 1, b0 + B) around the brick.  The workgroup takes every pixel whose
-// ray can cross that box (the detector bounding box of the box's projected
-// corners), marches only the ray's samples inside the box -- the same
-// sample points as the forward march -- and adds r * dt * weight to the
-// corners that fall in the brick with LDS atomics.  The brick is then written
-// once with plain stores, so no zeroing pass and no global atomics.
-constexpr int kBX = 16, kBY = 16, kBZ = 8;
-
-// Detector coordinates (mm along e_u, e_v) where the line from the source
-// through index-space point X meets the detector plane; false if X is not in
-// front of the source.
-__device__ __forceinline__ bool project_point(const RayGeom& g, const double X[3], double& u,
-                                              double& v)
+// ------------------------------------------------------------ support --
+// Index box of the nonzero voxels of an image: box = (min x, min y, min z,
+// max x, max y, max z), combined into `box` with atomics (the caller sets
+// it to (INT_MAX x3, INT_MIN x3) first).  NaN counts as nonzero.
+template <typename F>
+__global__ void __launch_bounds__(256) k_support(const F* __restrict__ f0, int nx, int ny, int nz,
+                                                 int* __restrict__ box)
 {
-    // solve S + t (X - S) = qc + u eu + v ev  (Cramer's rule)
-    double a[3], b[3], c[3], r[3];
-    for (int i = 0; i < 3; ++i) {
-        a[i] = X[i] - g.qs[i];
-        b[i] = -g.eu[i];
-        c[i] = -g.ev[i];
-        r[i] = g.qc[i] - g.qs[i];
+    __shared__ int sb[6];
+    if (threadIdx.x < 6) sb[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
+    __syncthreads();
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    const int nxy = nx * ny;
+    for (int z = blockIdx.y; z < nz; z += gridDim.y) {
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < nxy; e += gridDim.x * 256) {
+            const float v = widen<float>(f0[(size_t)z * nxy + e]);
+            if (!(v == 0.0f)) {
+                const int x = e % nx, y = e / nx;
+                lo[0] = min(lo[0], x); hi[0] = max(hi[0], x);
+                lo[1] = min(lo[1], y); hi[1] = max(hi[1], y);
+                lo[2] = min(lo[2], z); hi[2] = max(hi[2], z);
+            }
+        }
     }
-    auto det3 = [](const double* x, const double* y, const double* z) {
-        return x[0] * (y[1] * z[2] - y[2] * z[1]) - y[0] * (x[1] * z[2] - x[2] * z[1]) +
-               z[0] * (x[1] * y[2] - x[2] * y[1]);
-    };
-    double D = det3(a, b, c);
-    if (D == 0.0) return false;
-    double t = det3(r, b, c) / D;
-    if (!(t > 0.0)) return false;
-    u = det3(a, r, c) / D;
-    v = det3(a, b, r) / D;
-    return true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        atomicMin(&sb[a], lo[a]);
+        atomicMax(&sb[3 + a], hi[a]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) atomicMin(&box[threadIdx.x], sb[threadIdx.x]);
+    else if (threadIdx.x < 6) atomicMax(&box[threadIdx.x], sb[threadIdx.x]);
 }
+
+// out[row] = max |a[row][i]| over i < n, combined with atomics on the bit
+// patterns of the (non-negative) floats; the caller zeroes `out` first.
+template <typename S>
+__global__ void __launch_bounds__(256) k_absmax_rows(const S* __restrict__ a, size_t n,
+                                                     float* __restrict__ out)
+{
+    const S* row = a + (size_t)blockIdx.y * n;
+    float m = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(widen<float>(row[i])));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax((int*)&out[blockIdx.y], __float_as_int(m));
+}
+
+// ------------------------------------------------- gather backprojection --
+// P^T r as a gather: every output voxel sums, over the rays whose samples can
+// touch it, r * dt * (its trilinear weight) at each sample -- the weight the
+// forward march gives that voxel as a corner of the sample's cell, i.e.
+// prod_a max(0, 1 - |q_a - v_a|).  No atomics; each voxel accumulates in a
+// fixed order, so the result is deterministic.
+//
+// A workgroup owns a brick of 256 voxels (elongated along the rays'
+// dominant in-plane axis, which keeps its detector footprint small).  It
+// walks the footprint in 16 x 16 pixel tiles: per tile every thread stages
+// one ray in LDS -- the sample nearest the brick centre (relative to the
+// brick origin), the step per sample, its reciprocal, r dt and the valid
+// sample range [0, floor(L / dt)] -- then each voxel visits the rays of the
+// tile inside its own footprint (the detector box of its projected
+// (v - 1, v + 1)^3 neighbourhood) and, per ray, the samples whose slab test
+// puts them inside that neighbourhood.
+struct BPFoot {
+    // for an index-space point X: a = a0 + an.X (depth along the central
+    // ray, mm), b = b0 + bn.X and c = c0 + cn.X (offsets along e_u, e_v);
+    // it projects to u = sdd b / a + su, v = sdd c / a + sv (mm)
+    float a0, an[3], b0, bn[3], c0, cn[3];
+    float sdd, su, sv, u0, inv_du, v0, inv_dv;
+    int nu, nv;
+};
+
+// Pixel box (inclusive, clipped to the detector) that holds every ray
+// meeting the index-space box [lo, hi]; empty (i0 > i1) if none can.
+__device__ __forceinline__ void footprint(const BPFoot& F, const float lo[3], const float hi[3],
+                                          int& iu0, int& iu1, int& iv0, int& iv1)
+{
+    float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+    bool front = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float X = (c & 1) ? hi[0] : lo[0], Y = (c & 2) ? hi[1] : lo[1], Z = (c & 4) ? hi[2] : lo[2];
+        const float a = F.a0 + F.an[0] * X + F.an[1] * Y + F.an[2] * Z;
+        const float b = F.b0 + F.bn[0] * X + F.bn[1] * Y + F.bn[2] * Z;
+        const float cc = F.c0 + F.cn[0] * X + F.cn[1] * Y + F.cn[2] * Z;
+        front = front && a > 1e-3f;
+        const float t = F.sdd / a;
+        const float u = fmaf(t, b, F.su), v = fmaf(t, cc, F.sv);
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+    }
+    if (!front) {  // the box reaches behind the source: every pixel
+        iu0 = 0; iu1 = F.nu - 1; iv0 = 0; iv1 = F.nv - 1;
+        return;
+    }
+    // one pixel of margin on each side covers the FP32 rounding of the box
+    iu0 = max(0, (int)floorf(fmaxf((umin - F.u0) * F.inv_du, -2.0f)) - 1);
+    iu1 = min(F.nu - 1, (int)ceilf(fminf((umax - F.u0) * F.inv_du, (float)F.nu + 2.0f)) + 1);
+    iv0 = max(0, (int)floorf(fmaxf((vmin - F.v0) * F.inv_dv, -2.0f)) - 1);
+    iv1 = min(F.nv - 1, (int)ceilf(fminf((vmax - F.v0) * F.inv_dv, (float)F.nv + 2.0f)) + 1);
+}
+
+struct BPArgs {
+    RayGeom g;            // unswapped (x-fastest) geometry
+    BPFoot F;
+    int bx, by, bz;       // brick (bx * by * bz == 256)
+    int nbx, nby;         // bricks per axis
+    int nx, ny, nz;
+    double a, b, scale;   // r = scale (p - a y - b) when no residual is given
+};
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_backproject_brick(RayGeom g, int nbx, int nby,
-                                                           const R* __restrict__ resid,
-                                                           const R* __restrict__ p,
-                                                           const R* __restrict__ y, double a,
-                                                           double b, double scale,
-                                                           R* __restrict__ out, int nx, int ny,
-                                                           int nz)
+__global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* __restrict__ resid,
+                                                            const R* __restrict__ p,
+                                                            const R* __restrict__ y,
+                                                            R* __restrict__ out)
 {
-    __shared__ R acc[kBZ * kBY * kBX];
-    __shared__ int box[4];
+    __shared__ R s_q[3][256];      // nearest sample to the brick centre, minus the brick origin
+    __shared__ R s_d[3][256];      // index-space step per sample
+    __shared__ float s_inv[3][256];
+    __shared__ R s_rw[256];        // r dt
+    __shared__ int s_m[2][256];    // valid sample offsets [m0, m1] from that sample
+    __shared__ int s_box[4];
+    const RayGeom& g = A.g;
+    const int t = threadIdx.x;
     const int bid = blockIdx.x;
-    const int b0x = (bid % nbx) * kBX, b0y = ((bid / nbx) % nby) * kBY, b0z = (bid / (nbx * nby)) * kBZ;
-    for (int e = threadIdx.x; e < kBZ * kBY * kBX; e += 256) acc[e] = (R)0;
-    if (threadIdx.x == 0) {
-        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-        bool ok = true;
-        for (int c = 0; c < 8 && ok; ++c) {
-            double X[3] = {(double)(c & 1 ? b0x + kBX : b0x - 1), (double)(c & 2 ? b0y + kBY : b0y - 1),
-                           (double)(c & 4 ? b0z + kBZ : b0z - 1)};
-            double u, v;
-            ok = project_point(g, X, u, v);
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-            vmin = fmin(vmin, v);
-            vmax = fmax(vmax, v);
-        }
-        int iu0 = 0, iu1 = g.nu - 1, iv0 = 0, iv1 = g.nv - 1;
-        if (ok) {
-            iu0 = max(iu0, (int)fmax(floor((umin - g.u0) / g.du) - 1.0, -1.0));
-            iu1 = min(iu1, (int)fmin(ceil((umax - g.u0) / g.du) + 1.0, (double)g.nu));
-            iv0 = max(iv0, (int)fmax(floor((vmin - g.v0) / g.dv) - 1.0, -1.0));
-            iv1 = min(iv1, (int)fmin(ceil((vmax - g.v0) / g.dv) + 1.0, (double)g.nv));
-        }
-        box[0] = iu0;
-        box[1] = iu1;
-        box[2] = iv0;
-        box[3] = iv1;
+    const int b0[3] = {(bid % A.nbx) * A.bx, ((bid / A.nbx) % A.nby) * A.by, (bid / (A.nbx * A.nby)) * A.bz};
+    const int l[3] = {t % A.bx, (t / A.bx) % A.by, t / (A.bx * A.by)};
+    const int v[3] = {b0[0] + l[0], b0[1] + l[1], b0[2] + l[2]};
+    const bool inside = v[0] < A.nx && v[1] < A.ny && v[2] < A.nz;
+    if (t == 0) {
+        const float lo[3] = {(float)(b0[0] - 1), (float)(b0[1] - 1), (float)(b0[2] - 1)};
+        const float hi[3] = {(float)(b0[0] + A.bx), (float)(b0[1] + A.by), (float)(b0[2] + A.bz)};
+        footprint(A.F, lo, hi, s_box[0], s_box[1], s_box[2], s_box[3]);
+    }
+    int ru0 = 0, ru1 = -1, rv0 = 0, rv1 = -1;
+    if (inside) {
+        const float lo[3] = {(float)(v[0] - 1), (float)(v[1] - 1), (float)(v[2] - 1)};
+        const float hi[3] = {(float)(v[0] + 1), (float)(v[1] + 1), (float)(v[2] + 1)};
+        footprint(A.F, lo, hi, ru0, ru1, rv0, rv1);
     }
     __syncthreads();
-    const int iu0 = box[0], nub = box[1] - box[0] + 1, iv0 = box[2], nvb = box[3] - box[2] + 1;
-    const int nr = (nub > 0 && nvb > 0) ? nub * nvb : 0;
-    const R lo[3] = {(R)(b0x - 1), (R)(b0y - 1), (R)(b0z - 1)};
-    const R hi[3] = {(R)(b0x + kBX), (R)(b0y + kBY), (R)(b0z + kBZ)};
-    const R fn1[3] = {(R)(nx + 1), (R)(ny + 1), (R)(nz + 1)};
-    // each thread takes a contiguous run of the box's pixels, so that the
-    // 64 lanes of a wave march rays ~nr/256 pixels apart whose samples fall
-    // on different voxels (no same-address LDS atomics within one wave)
-    const int chunk = (nr + 255) / 256;
-    const int r_begin = threadIdx.x * chunk, r_end = min(nr, r_begin + chunk);
-    for (int rr = r_begin; rr < r_end; ++rr) {
-        const int iu = iu0 + rr % nub, iv = iv0 + rr / nub;
-        const size_t pix = iu + (size_t)g.nu * iv;
-        R r = resid ? resid[pix] : (R)(scale * ((double)p[pix] - a * (double)y[pix] - b));
-        if (r == (R)0) continue;
-        RaySeg<R> rs = ray_segment<R>(g, iu, iv, 1, 0);
-        if (rs.count == 0) continue;
-        // samples of this ray inside the box (one sample of margin each side)
-        double mlo = 0.0, mhi = (double)(rs.count - 1);
-        bool miss = false;
+    const int bu0 = s_box[0], bu1 = s_box[1], bv0 = s_box[2], bv1 = s_box[3];
+    const double cb[3] = {b0[0] + 0.5 * (A.bx - 1), b0[1] + 0.5 * (A.by - 1), b0[2] + 0.5 * (A.bz - 1)};
+    const R lr[3] = {(R)l[0], (R)l[1], (R)l[2]};
+    R acc = (R)0;
+    for (int tv0 = bv0; tv0 <= bv1; tv0 += 16) {
+        for (int tu0 = bu0; tu0 <= bu1; tu0 += 16) {
+            {   // stage one ray per thread (FP64 set-up, once per ray and brick)
+                const int iu = tu0 + (t & 15), iv = tv0 + (t >> 4);
+                int m0 = 1, m1 = 0;
+                R rw = (R)0;
+                double qr[3] = {0.0, 0.0, 0.0}, dq[3] = {0.0, 0.0, 0.0};
+                if (iu <= bu1 && iv <= bv1) {
+                    const size_t pix = iu + (size_t)g.nu * iv;
+                    const double r = resid ? (double)resid[pix]
+                                           : A.scale * ((double)p[pix] - A.a * (double)y[pix] - A.b);
+                    const double uu = g.u0 + iu * g.du, vv = g.v0 + iv * g.dv;
+                    double D[3], L2 = 0.0;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            double q0 = (double)rs.q0[ax], d = (double)rs.dq[ax];
-            if (d != 0.0) {
-                double m1 = ((double)lo[ax] - q0) / d, m2 = ((double)hi[ax] - q0) / d;
-                mlo = fmax(mlo, floor(fmin(m1, m2)) - 1.0);
-                mhi = fmin(mhi, ceil(fmax(m1, m2)) + 1.0);
-            } else if (q0 < (double)lo[ax] - 1.0 || q0 > (double)hi[ax] + 1.0) {
-                miss = true;
-            }
-        }
-        if (miss || mlo > mhi) continue;
-        const R rw = r * (R)g.dt;
-        const R q0x = rs.q0[0] + (R)1, q0y = rs.q0[1] + (R)1, q0z = rs.q0[2] + (R)1;
-        for (int m = (int)mlo; m <= (int)mhi; ++m) {
-            const R fm = (R)m;
-            // identical arithmetic to the forward march (padded index space)
-            R qx = clampv(fma(fm, rs.dq[0], q0x), (R)0, fn1[0]);
-            R qy = clampv(fma(fm, rs.dq[1], q0y), (R)0, fn1[1]);
-            R qz = clampv(fma(fm, rs.dq[2], q0z), (R)0, fn1[2]);
-            const int ix = (int)qx - 1 - b0x, iy = (int)qy - 1 - b0y, iz = (int)qz - 1 - b0z;
-            if (ix < -1 || ix >= kBX || iy < -1 || iy >= kBY || iz < -1 || iz >= kBZ) continue;
-            const R ax = qx - floor(qx), ay = qy - floor(qy), az = qz - floor(qz);
-            const R bx = (R)1 - ax, by = (R)1 - ay, bz = (R)1 - az;
-            const R wyz[4] = {by * bz, ay * bz, by * az, ay * az};
+                    for (int ax = 0; ax < 3; ++ax) {
+                        D[ax] = g.qc[ax] + uu * g.eu[ax] + vv * g.ev[ax] - g.qs[ax];
+                        const double w = D[ax] * g.sp[ax];
+                        L2 += w * w;
+                    }
+                    if (L2 > 0.0 && r != 0.0) {
+                        const double L = sqrt(L2), invL = 1.0 / L;
+                        double tc = 0.0;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int dx = t & 1, dy = (t >> 1) & 1, dz = t >> 2;
-                const int tx = ix + dx, ty = iy + dy, tz = iz + dz;
-                if ((unsigned)tx < (unsigned)kBX && (unsigned)ty < (unsigned)kBY &&
-                    (unsigned)tz < (unsigned)kBZ)
-                    atomicAdd(&acc[(tz * kBY + ty) * kBX + tx], ((dx ? ax : bx) * wyz[dy + 2 * dz]) * rw);
+                        for (int ax = 0; ax < 3; ++ax) {
+                            D[ax] *= invL;   // index units per mm
+                            tc += (cb[ax] - g.qs[ax]) * g.sp[ax] * g.sp[ax] * D[ax];
+                        }
+                        const double nlast = floor(L / g.dt);
+                        const double nc = fmin(fmax(rint(tc / g.dt), 0.0), nlast);
+                        const double tn = nc * g.dt;
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            qr[ax] = g.qs[ax] + tn * D[ax] - (double)b0[ax];
+                            dq[ax] = g.dt * D[ax];
+                        }
+                        m0 = -(int)nc;
+                        m1 = (int)(nlast - nc);
+                        rw = (R)(r * g.dt);
+                    }
+                }
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    s_q[ax][t] = (R)qr[ax];
+                    s_d[ax][t] = (R)dq[ax];
+                    const float df = (float)dq[ax];
+                    s_inv[ax][t] = fabsf(df) > 1e-30f ? 1.0f / df : 1.0e30f;
+                }
+                s_rw[t] = rw;
+                s_m[0][t] = m0;
+                s_m[1][t] = m1;
             }
+            __syncthreads();
+            const int ua = max(ru0, tu0), ub = min(ru1, tu0 + 15);
+            const int va = max(rv0, tv0), vb = min(rv1, tv0 + 15);
+            for (int iv = va; iv <= vb; ++iv) {
+                for (int iu = ua; iu <= ub; ++iu) {
+                    const int k = ((iv - tv0) << 4) + (iu - tu0);
+                    const R rx = s_q[0][k] - lr[0], ry = s_q[1][k] - lr[1], rz = s_q[2][k] - lr[2];
+                    const R dx = s_d[0][k], dy = s_d[1][k], dz = s_d[2][k];
+                    // samples m with |r + m d| < 1 on every axis (slab test,
+                    // widened to whole samples; the weights clip the rest)
+                    float lo = -1.0e6f, hi = 1.0e6f;
+                    {
+                        const float ix = s_inv[0][k], iy = s_inv[1][k], iz = s_inv[2][k];
+                        const float ex1 = (-1.0f - (float)rx) * ix, ex2 = (1.0f - (float)rx) * ix;
+                        const float ey1 = (-1.0f - (float)ry) * iy, ey2 = (1.0f - (float)ry) * iy;
+                        const float ez1 = (-1.0f - (float)rz) * iz, ez2 = (1.0f - (float)rz) * iz;
+                        lo = fmaxf(lo, fmaxf(fminf(ex1, ex2), fmaxf(fminf(ey1, ey2), fminf(ez1, ez2))));
+                        hi = fminf(hi, fminf(fmaxf(ex1, ex2), fminf(fmaxf(ey1, ey2), fmaxf(ez1, ez2))));
+                    }
+                    lo = fminf(lo, 1.0e6f);    // |m| stays far inside int range
+                    hi = fmaxf(hi, -1.0e6f);
+                    const int m0 = max(s_m[0][k], (int)floorf(lo));
+                    const int m1 = min(s_m[1][k], (int)ceilf(hi));
+                    const R rw = s_rw[k];
+                    for (int m = m0; m <= m1; ++m) {
+                        const R fm = (R)m;
+                        const R wx = fmax((R)0, (R)1 - fabs(fma(fm, dx, rx)));
+                        const R wy = fmax((R)0, (R)1 - fabs(fma(fm, dy, ry)));
+                        const R wz = fmax((R)0, (R)1 - fabs(fma(fm, dz, rz)));
+                        acc = fma(wx * wy * wz, rw, acc);
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kBZ * kBY * kBX; e += 256) {
-        const int lx = e % kBX, ly = (e / kBX) % kBY, lz = e / (kBX * kBY);
-        const int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
-        if (gx < nx && gy < ny && gz < nz)
-            out[(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)] = acc[e];
-    }
+    if (inside) out[(size_t)v[0] + (size_t)A.nx * ((size_t)v[1] + (size_t)A.ny * v[2])] = acc;
 }
 
 // ---------------------------------------------------------- contraction --
@@ -1018,6 +1191,8 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
         r.eu[a] = eu[a] / g.spacing_mm[a];
         r.ev[a] = ev[a] / g.spacing_mm[a];
         r.lim[a] = (double)g.n[a];
+        r.clo[a] = -1.0;
+        r.chi[a] = r.lim[a];
     }
     if (swap_xy) {
         std::swap(r.sp[0], r.sp[1]);
@@ -1026,6 +1201,7 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
         std::swap(r.eu[0], r.eu[1]);
         std::swap(r.ev[0], r.ev[1]);
         std::swap(r.lim[0], r.lim[1]);
+        std::swap(r.chi[0], r.chi[1]);
     }
     r.u0 = -0.5 * (G.nu - 1) * G.du_mm + G.off_u_mm;
     r.v0 = -0.5 * (G.nv - 1) * G.dv_mm + G.off_v_mm;
@@ -1131,13 +1307,17 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
     dim3 grid = vox_grid(g), blk(64, 4);
     auto w = wvec(w_eff, K);
     dim3 grid_yf((g.n[0] + 31) / 32, (g.n[1] + 31) / 32, g.n[2]);
-#define PCR_WF(C, T)                                                                              \
-    (L.yfast ? k_warp_fused_yf<R, S, F, C, T><<<grid_yf, 256, 0, s>>>(                            \
-                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py,           \
-                   (Chan<R, C>*)padded)                                                           \
-             : k_warp_fused<R, S, F, C, T><<<grid, blk, 0, s>>>((const F*)f0, (const S*)mean,      \
-                                                                (const S*)U, K, w, vox(g), L.px,  \
-                                                                L.py, (Chan<R, C>*)padded))
+    Chan<float, 8> hs;
+    for (int c = 0; c < 8; ++c) hs.v[c] = L.hs[c];
+#define PCR_WF2(C, T, H)                                                                          \
+    (L.yfast ? k_warp_fused_yf<R, S, F, C, T, H><<<grid_yf, 256, 0, s>>>(                         \
+                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs,       \
+                   (CellOf<R, C, H>*)padded)                                                      \
+             : k_warp_fused<R, S, F, C, T, H><<<grid, blk, 0, s>>>(                               \
+                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs,       \
+                   (CellOf<R, C, H>*)padded))
+#define PCR_WF(C, T) (L.half ? PCR_WF2(C, T, true) : PCR_WF2(C, T, false))
+    if (L.half && !std::is_same<R, float>::value) return hipErrorInvalidValue;
     if (!tangent) {
         switch (L.C) {
         case 1: PCR_WF(1, false); break;
@@ -1155,6 +1335,7 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
         }
     }
 #undef PCR_WF
+#undef PCR_WF2
     return hipGetLastError();
 }
 
@@ -1231,7 +1412,8 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     if (moments) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_reduce<<<1, 1024, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
+        k_reduce<<<1, 1024, 0, s>>>(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C),
+                                moments);
     }
     return hipGetLastError();
 }
@@ -1245,12 +1427,14 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.ms = ms;
     A.tiles_u = tiles_u_of(rg, ms);
     A.vol = padded;
-    A.vol_bytes = (unsigned)(L.cells() * (size_t)L.C * 4);
+    const int cb = (int)L.cell_bytes(4);
+    A.vol_bytes = (unsigned)(L.cells() * (size_t)cb);
     A.px = L.px;
     A.py = L.py;
     A.pz = L.pz;
-    A.ys = L.px * L.C * 4;
-    A.zs = L.px * L.py * L.C * 4;
+    A.ys = L.px * cb;
+    A.zs = L.px * L.py * cb;
+    for (int c = 0; c < 8; ++c) A.ihs[c] = 1.0f / L.hs[c];
     for (int a = 0; a < 3; ++a) A.fn1[a] = (float)(rg.lim[a] + 1.0);
     A.kc = kc;
     A.y = (const float*)y;
@@ -1260,9 +1444,16 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.counter = counter;
     int blocks = march_blocks(rg, ms);
     const bool buf = ms.buffer_loads;
-#define PCR_MF(C) (buf ? k_march_f32<C, true><<<blocks, 256, 0, s>>>(A) : k_march_f32<C, false><<<blocks, 256, 0, s>>>(A))
+#define PCR_MF(C)                                                                                 \
+    (L.half ? k_march_f32<C, false, true><<<blocks, 256, 0, s>>>(A)                               \
+     : buf  ? k_march_f32<C, true, false><<<blocks, 256, 0, s>>>(A)                               \
+            : k_march_f32<C, false, false><<<blocks, 256, 0, s>>>(A))
+    if (L.half && L.C == 1) return hipErrorInvalidValue;
     switch (L.C) {
-    case 1: PCR_MF(1); break;
+    case 1:
+        if (buf) k_march_f32<1, true, false><<<blocks, 256, 0, s>>>(A);
+        else k_march_f32<1, false, false><<<blocks, 256, 0, s>>>(A);
+        break;
     case 2: PCR_MF(2); break;
     case 4: PCR_MF(4); break;
     case 8: PCR_MF(8); break;
@@ -1271,7 +1462,8 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
 #undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
-    k_reduce<<<1, 1024, 0, s>>>(partials, blocks, 5 + 3 * (L.C - 1), n_moments(kc), moments);
+    k_reduce<<<1, 1024, 0, s>>>(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C),
+                                moments);
     return hipGetLastError();
 }
 
@@ -1289,7 +1481,7 @@ hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const Ray
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
                          hipStream_t s)
 {
-    k_reduce<<<1, 1024, 0, s>>>(partials, nblocks, stride, nm, out);
+    k_reduce<<<1, 1024, 0, s>>>(partials, nblocks, stride, nm, -1, out);
     return hipGetLastError();
 }
 
@@ -1297,13 +1489,62 @@ hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeo
                               const void* resid, const void* p, const void* y, double a, double b,
                               double scale, void* out, hipStream_t s)
 {
-    const int nbx = (g.n[0] + kBX - 1) / kBX, nby = (g.n[1] + kBY - 1) / kBY,
-              nbz = (g.n[2] + kBZ - 1) / kBZ;
-    const unsigned blocks = (unsigned)(nbx * nby * nbz);
+    BPArgs A;
+    A.g = rg;
+    // footprint geometry (physical, mm): n = unit vector source -> detector
+    // centre, e_u / e_v the detector axes; for X in index space the offset
+    // from the source is (X - qs) * sp
+    double n[3], eu[3], ev[3], nn = 0.0, sdd;
+    for (int ax = 0; ax < 3; ++ax) {
+        n[ax] = (rg.qc[ax] - rg.qs[ax]) * rg.sp[ax];
+        nn += n[ax] * n[ax];
+        eu[ax] = rg.eu[ax] * rg.sp[ax];
+        ev[ax] = rg.ev[ax] * rg.sp[ax];
+    }
+    sdd = std::sqrt(nn);
+    if (!(sdd > 0.0)) return hipErrorInvalidValue;
+    double a0 = 0.0, b0 = 0.0, c0 = 0.0, su = 0.0, sv = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        n[ax] /= sdd;
+        A.F.an[ax] = (float)(rg.sp[ax] * n[ax]);
+        A.F.bn[ax] = (float)(rg.sp[ax] * eu[ax]);
+        A.F.cn[ax] = (float)(rg.sp[ax] * ev[ax]);
+        a0 -= rg.qs[ax] * rg.sp[ax] * n[ax];
+        b0 -= rg.qs[ax] * rg.sp[ax] * eu[ax];
+        c0 -= rg.qs[ax] * rg.sp[ax] * ev[ax];
+        su += (rg.qs[ax] - rg.qc[ax]) * rg.sp[ax] * eu[ax];
+        sv += (rg.qs[ax] - rg.qc[ax]) * rg.sp[ax] * ev[ax];
+    }
+    A.F.a0 = (float)a0;
+    A.F.b0 = (float)b0;
+    A.F.c0 = (float)c0;
+    A.F.sdd = (float)sdd;
+    A.F.su = (float)su;
+    A.F.sv = (float)sv;
+    A.F.u0 = (float)rg.u0;
+    A.F.inv_du = (float)(1.0 / rg.du);
+    A.F.v0 = (float)rg.v0;
+    A.F.inv_dv = (float)(1.0 / rg.dv);
+    A.F.nu = rg.nu;
+    A.F.nv = rg.nv;
+    // bricks elongated along the rays' dominant in-plane axis
+    const double rx = std::fabs(rg.qc[0] - rg.qs[0]) * rg.sp[0], ry = std::fabs(rg.qc[1] - rg.qs[1]) * rg.sp[1];
+    if (ry >= rx) { A.bx = 4; A.by = 16; } else { A.bx = 16; A.by = 4; }
+    A.bz = 4;
+    A.nx = g.n[0];
+    A.ny = g.n[1];
+    A.nz = g.n[2];
+    A.nbx = (A.nx + A.bx - 1) / A.bx;
+    A.nby = (A.ny + A.by - 1) / A.by;
+    const int nbz = (A.nz + A.bz - 1) / A.bz;
+    A.a = a;
+    A.b = b;
+    A.scale = scale;
+    const long blocks = (long)A.nbx * A.nby * nbz;
+    if (blocks <= 0 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     PCR_DISPATCH_R(compute, R,
-        k_backproject_brick<R><<<blocks, 256, 0, s>>>(rg, nbx, nby, (const R*)resid, (const R*)p,
-                                                      (const R*)y, a, b, scale, (R*)out, g.n[0],
-                                                      g.n[1], g.n[2]));
+        k_backproject_gather<R><<<(unsigned)blocks, 256, 0, s>>>(A, (const R*)resid, (const R*)p,
+                                                                (const R*)y, (R*)out));
     return hipGetLastError();
 }
 
@@ -1326,6 +1567,26 @@ hipError_t launch_warp_adjoint(pcr_dtype compute, const pcr_grid& g, const void*
     PCR_DISPATCH_R(compute, R,
         k_warp_adjoint<R><<<vox_grid(g), dim3(64, 4), 0, s>>>((const R*)dvf, (const R*)gv, vox(g),
                                                               (R*)out));
+    return hipGetLastError();
+}
+
+hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* box,
+                          hipStream_t s)
+{
+    const long nxy = (long)g.n[0] * g.n[1];
+    const unsigned bx = (unsigned)std::min<long>((nxy + 255) / 256, 64);
+    const unsigned bz = (unsigned)std::min(g.n[2], 256);
+    PCR_DISPATCH_S(f0_dtype, F,
+        k_support<F><<<dim3(bx, bz), 256, 0, s>>>((const F*)f0, g.n[0], g.n[1], g.n[2], box));
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax_rows(pcr_dtype dt, const void* a, size_t n, int rows, float* out,
+                              hipStream_t s)
+{
+    const unsigned bx = (unsigned)std::min<size_t>((n + 255) / 256, 512);
+    PCR_DISPATCH_S(dt, S,
+        k_absmax_rows<S><<<dim3(bx, (unsigned)rows), 256, 0, s>>>((const S*)a, n, out));
     return hipGetLastError();
 }
 

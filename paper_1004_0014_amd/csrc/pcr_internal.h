@@ -23,12 +23,26 @@ namespace pcr {
 // march then reads a geometry with x and y swapped, so that detector rows
 // (which run along e_u = (cos t, sin t, 0)) walk the fastest memory axis at
 // every gantry angle.  px, py are the padded dims in memory order.
+//
+// Channels are stored in the compute type, or (FP32 compute, `half`) as FP16
+// holding value * hs[c], with hs[c] a power of two chosen from a bound on the
+// channel's magnitude so that no value overflows; the march multiplies its
+// sums by 1 / hs[c] (exact).
 struct PadLayout {
     int nx, ny, nz;
     int px, py, pz;      // padded dims in memory order (fast, mid, slow)
     int C;               // channel stride (1, 2, 4 or 8)
     bool yfast;
+    bool half = false;   // FP16 channels (FP32 compute only)
+    float hs[8] = {1, 1, 1, 1, 1, 1, 1, 1};
     size_t cells() const { return (size_t)px * py * pz; }
+    size_t cell_bytes(size_t compute_size) const { return (size_t)C * (half ? 2 : compute_size); }
+    // same memory image: a buffer laid out for one is laid out for the other
+    bool same_storage(const PadLayout& o) const
+    {
+        return nx == o.nx && ny == o.ny && nz == o.nz && C == o.C && yfast == o.yfast &&
+               half == o.half;
+    }
 };
 PadLayout make_pad(const pcr_grid& g, int C, bool yfast = false);
 // y-fastest storage when the detector's u axis is closer to y than to x
@@ -43,6 +57,10 @@ struct RayGeom {
     double eu[3], ev[3]; // detector axes (index units per mm)
     double sp[3];        // voxel spacing (mm)
     double lim[3];       // upper support bound n_a (the lower one is -1)
+    double clo[3], chi[3]; // box the rays are clipped to: the support (-1, n_a) by
+                           // default, or a tighter box outside which the
+                           // image is known to be zero (no sample there
+                           // contributes)
     double u0, v0;       // detector coordinate (mm) of pixel 0 along e_u, e_v
     double du, dv;       // pixel pitch (mm)
     double dt;           // sample spacing (mm)
@@ -64,6 +82,8 @@ MarchShape choose_march_shape(const RayGeom& rg);
 //   5+3k sum p t_k, 6+3k sum y t_k, 7+3k sum t_k,
 // with p = P f and t_k = P h_k per ray.  FP64.
 inline int n_moments(int kc) { return 5 + 3 * (kc - 1); }
+// with moments != null the march also returns, after the n_moments(kc)
+// moments, the number of ray samples it marched
 constexpr int kMaxMoments = 5 + 3 * 8;
 
 int march_blocks(const RayGeom& rg, const MarchShape& ms);
@@ -93,6 +113,13 @@ hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const Ray
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
                         double* partials, double* moments, unsigned* counter, hipStream_t s);
 // Fixed-order final sum of per-block partials: out[m] for m < nm.
+// Index box of the nonzero voxels of f0 into box[6] (min xyz, max xyz; the
+// caller initialises it to INT_MAX x3, INT_MIN x3).
+hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* box,
+                          hipStream_t s);
+// out[r] = max_i |a[r][i]| for `rows` rows of n values (out zeroed by the caller).
+hipError_t launch_absmax_rows(pcr_dtype dt, const void* a, size_t n, int rows, float* out,
+                              hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
                          hipStream_t s);
 // Backprojection out = P^T r (unpadded [N], fully overwritten) with r = resid

@@ -50,6 +50,7 @@ struct Stream {
     size_t bytes = 0;
     size_t scratch = 0;
     int queued = 0;
+    Support sup;
 };
 
 struct Request {
@@ -126,6 +127,7 @@ bool pcr_server::start_slot(Slot& sl)
 {
     Stream* st = sl.st;
     sl.E = Evaluator{&st->grid, &st->model, st->f0_dtype, PCR_F32, st->f0.p, &sl.sc, sl.s};
+    sl.E.sup = &st->sup;
     sl.t_start = now_s();
     for (int k = 0; k < 8; ++k) sl.w0[k] = k < st->model.K ? st->w[k] : 0.0;
     if (o.predict_order > 0 && st->nhist >= 2) {
@@ -379,6 +381,8 @@ pcr_status pcr_server_add_stream(pcr_server* S, const pcr_grid* grid, const pcr_
     st->model.mean = st->mean.p;
     st->model.U = st->U.p;
     st->model.scale = model->scale ? st->scale : nullptr;
+    e = compute_support(st->grid, st->model, st->f0_dtype, st->f0.p, S->device, nullptr, &st->sup);
+    if (e != PCR_OK) return unreserve(e);
     std::lock_guard<std::mutex> lk(S->mu);
     st->id = S->next_sid++;
     *stream_id = st->id;

@@ -77,12 +77,14 @@ def gpu_phantom(grid, seed, dev):
     mu[inside(tc, (10.0, 10.0, 10.0))] = 0.02
     g = torch.Generator(device=dev).manual_seed(seed)
     z = torch.randn(grid.shape, generator=g, device=dev, dtype=torch.float32)
-    k = torch.exp(-0.5 * torch.arange(-4, 5, device=dev, dtype=torch.float32) ** 2)
+    k = np.exp(-0.5 * np.arange(-4, 5) ** 2)
     k = k / k.sum()
-    z = z[None, None]
-    z = torch.nn.functional.conv3d(z, k.view(1, 1, 9, 1, 1), padding=(4, 0, 0))
-    z = torch.nn.functional.conv3d(z, k.view(1, 1, 1, 9, 1), padding=(0, 4, 0))
-    z = torch.nn.functional.conv3d(z, k.view(1, 1, 1, 1, 9), padding=(0, 0, 4))[0, 0]
+    for ax in range(3):           # separable Gaussian (sigma = 1 voxel), zero padded
+        n = z.shape[ax]
+        pad = [0, 0] * 3
+        pad[2 * (2 - ax)] = pad[2 * (2 - ax) + 1] = 4
+        zp = torch.nn.functional.pad(z, pad)
+        z = sum(float(k[j]) * zp.narrow(ax, j, n) for j in range(9))
     z = z / z.std()
     return (mu * (1.0 + 0.05 * z)).contiguous(), np.array(tc)
 
@@ -108,13 +110,14 @@ def gpu_model(grid, K, dev):
     Lc = np.linalg.cholesky(Q)
     A, _, _ = np.linalg.svd(Lc.T @ (C - cbar[:, None]), full_matrices=False)
     Z = np.linalg.solve(Lc.T, A)[:, :K]
-    U = (torch.tensor(Z.T, dtype=torch.float32, device=dev) @ Pf).view((K, 3) + grid.shape)
+    U = torch.stack([sum(float(Z[j, k]) * Pf[j] for j in range(K)) for k in range(K)]).view(
+        (K, 3) + grid.shape)
     for k in range(K):
         j = int(torch.argmax(U[k].abs()))
         if float(U[k].reshape(-1)[j]) < 0:
             U[k] = -U[k]
             Z[:, k] = -Z[:, k]
-    mean = (torch.tensor(cbar, dtype=torch.float32, device=dev) @ Pf).view((3,) + grid.shape)
+    mean = sum(float(cbar[j]) * Pf[j] for j in range(K)).view((3,) + grid.shape)
     w_train = (C - cbar[:, None]).T @ Q @ Z
     step0 = 0.5 * float(np.sqrt(np.mean(np.sum(w_train ** 2, axis=1))))
     return mean.contiguous(), U.contiguous(), dict(Z=Z, Q=Q, cbar=cbar, step0=step0)

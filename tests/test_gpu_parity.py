@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_1004_0014_amd import synth as S
-from helpers import Case, rel_l2, rounded
+from helpers import Case, rel_l2, rounded, support_box_samples
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -332,4 +332,58 @@ def test_invalid_inputs_rejected():
     y = torch.ones((4, 4), device=DEV)
     with pytest.raises(L.PCRError):
         ctx.reconstruct(y, S.Geom(0.0, 4, 4, 1.0, 1.0, 0.5), [0.0, 0.0], L.default_opts(step0=0.0))
+    ctx.close()
+
+
+# ----------------------------------------------------- clipped rays -------
+def _blob_case(zero=False):
+    """A compact object in a large grid (so that rays are clipped to a box
+    much smaller than the grid) under a model with large displacements."""
+    g = S.Grid((48, 40, 36), (4.0, 4.5, 5.0))
+    idx = np.indices(g.shape).astype(float)          # (z, y, x)
+    r2 = ((idx[2] - 20) / 7.0) ** 2 + ((idx[1] - 17) / 6.0) ** 2 + ((idx[0] - 15) / 5.0) ** 2
+    f0 = np.where(r2 <= 1.0, 0.02 * (1.0 + 0.1 * np.cos(idx[2])), 0.0)
+    if zero:
+        f0[:] = 0.0
+    K = 2
+    U = np.zeros((K, 3) + g.shape)
+    U[0, 2] = np.exp(-r2 / 4.0)
+    U[1, 0] = np.exp(-r2 / 6.0) * (idx[0] - 15) / 10.0
+    U /= np.linalg.norm(U.reshape(K, -1), axis=1)[:, None, None, None, None]
+    mean = np.zeros((3,) + g.shape)
+    mean[1] = 1.5 * np.exp(-r2 / 9.0)
+    return g, f0, mean, U
+
+
+@pytest.mark.parametrize("zero", [False, True])
+def test_clipped_rays_are_exact(zero):
+    """Rays are clipped to the box where the warped image can be nonzero;
+    J, its gradient and a solve still follow the oracle (which marches the
+    whole support box), and fewer samples are marched."""
+    L = _lib()
+    g, f0, mean, U = _blob_case(zero)
+    f0_t, f0r = rounded(f0, torch.float32)
+    mean_t, meanr = rounded(mean, torch.float32)
+    U_t, Ur = rounded(U, torch.float32)
+    dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV))
+    G = S.Geom(math.radians(71.0), 96, 80, 2.6, 2.6, 2.0)
+    rng = np.random.default_rng(5)
+    y_np = rng.uniform(0.0, 1.0, (G.nv, G.nu))
+    y = torch.tensor(y_np, dtype=torch.float32, device=DEV)
+    y_np = y.double().cpu().numpy()
+    ctx = L.Context(g, dm, f0_t.to(DEV))
+    nrm = np.sqrt(np.sum(U.reshape(2, -1) ** 2, axis=1))
+    for w in ([40.0, -25.0], [0.0, 0.0], [-90.0, 60.0]):
+        J, grad = ctx.cost_grad(y, G, w, 0.8, 0.1)
+        Jo, go = oracle.cost_grad(g, G, f0r, meanr, Ur, w, y_np, 0.8, 0.1)
+        assert abs(J - Jo) <= 2e-5 * Jo
+        if zero:
+            assert np.all(np.asarray(grad) == 0.0)
+        else:
+            assert rel_l2(grad, go) <= 1e-4
+    opts = L.default_opts(max_iter=6, step0=1.0)
+    w, ab, st = ctx.reconstruct(y, G, [0.0, 0.0], opts)
+    evals = st["trials"] + 1          # the evaluation at w0, then one per trial
+    full = support_box_samples(g, G)
+    assert 0 <= st["samples"] < 0.7 * full * evals
     ctx.close()
