@@ -33,9 +33,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "p50/p99 per-projection solve latency; solves/s served; ray-samples/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed-FP32 instructions (which this build disables):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# FP32 VALU issue rate without packed-FP32 instructions (which this build
+# disables): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+# (78.6 TFLOP/s counting an FMA as two flops).
+VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# vector L1 delivery: 64 B per clock per CU
+L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -232,7 +235,21 @@ def kernel_table(prof):
             for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
 
-def roofline(W, prof, samples_per_proj, channels):
+def profiled_traffic(name):
+    """HBM bytes per launch measured with rocprofv3 counters, from the line
+    `traffic_bytes_per_launch: <n>` of profiles/<name>.md (None if absent)."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    try:
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch:"):
+                v = line.split(":", 1)[1].strip()
+                return None if v in ("", "null", "None") else float(v)
+    except OSError:
+        pass
+    return None
+
+
+def roofline(W, prof, samples_per_launch, channels, cell_bytes, traffic_profile=None):
     """Roofline of the dominant kernel (largest total time in the timed region)."""
     kt = kernel_table(prof)
     dom = next(iter(kt))
@@ -242,21 +259,27 @@ def roofline(W, prof, samples_per_proj, channels):
     K = W.K
     avg_s = kt[dom]["avg_us"] * 1e-6
     if dom == "march":
-        # per sample: 3 position FMAs, clamp (6), floor (3), fractions (3),
-        # complements (3), 4 yz-weight products, then per channel 4 x-lerps
-        # (mul + FMA) and 4 weighted FMAs (12 ops, 2 flops per FMA counted as
-        # one op here: a VALU issue slot) -> 25 + 12 C VALU ops
-        ops = samples_per_proj * (25 + 12 * channels)
+        # VALU lane-instructions per sample (the loop as compiled): position
+        # FMAs, clamp, truncation, fractions and complements, the 8 trilinear
+        # weights (12 multiplies), then 8 FMAs per channel -> 25 + 12 C (72
+        # for C = 4 in the gfx950 code); an FMA is one issue slot here
+        ops = samples_per_launch * (25 + 12 * channels)
         achieved = ops / avg_s / 1e12
-        return {"kernel": dom, "bound": "alu", "achieved": achieved,
-                "peak": VALU_F32_PEAK_TFLOPS / 2, "unit": "TOP/s (VALU issue, fp32)",
-                "frac": achieved / (VALU_F32_PEAK_TFLOPS / 2),
-                "traffic": None, "avg_us": kt[dom]["avg_us"],
+        peak = VALU_ISSUE_PEAK_TOPS
+        # the cache path: 8 cells per sample through the vector L1
+        l1_bytes = samples_per_launch * 8 * cell_bytes
+        return {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TOP/s (fp32 VALU lane-instructions)", "frac": achieved / peak,
+                "traffic": profiled_traffic(traffic_profile) if traffic_profile else None,
+                "avg_us": kt[dom]["avg_us"], "samples_per_launch": samples_per_launch,
                 "algorithmic_ops_per_launch": ops,
-                "compulsory_hbm_bytes_per_launch": cells * 4 * channels + 4 * 196608}
+                "l1_bytes_per_launch": l1_bytes,
+                "l1_achieved_TBps": l1_bytes / avg_s / 1e12, "l1_peak_TBps": L1_PEAK_TBPS,
+                "l1_frac": l1_bytes / avg_s / 1e12 / L1_PEAK_TBPS,
+                "compulsory_hbm_bytes_per_launch": cells * cell_bytes + 4 * W.cfg["nu"] * W.cfg["nv"]}
     if dom == "warp_fused":
-        # reads mean (3) and U (3K) fields and f0 once, writes C channels
-        byts = N * (4 * 3 + 4 * 3 * K + 4 + 4 * channels)
+        # reads mean (3) and U (3K) fields and f0 once, writes the cells
+        byts = N * (4 * 3 + 4 * 3 * K + 4 + cell_bytes)
         achieved = byts / avg_s / 1e9
         return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -300,7 +323,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=360)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c1")
+    ap.add_argument("--config", default="paper")
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
     ap.add_argument("--variants", default="bf16,adjoint,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
@@ -357,7 +380,8 @@ def main():
                                           "mean_iterations", "mean_trials")},
         "kernels": kernel_table(res["prof"]),
         "roofline": roofline(W, res["prof"],
-                             float(np.sum(res["samples"])) / max(res["prof"]["march"][1], 1), channels),
+                             float(np.sum(res["samples"])) / max(res["prof"]["march"][1], 1), channels,
+                             4 * channels, "march_fused_%dx%dx%d_f32" % tuple(W.grid.n)),
     }
     log("[bench] main: %.1f solves/s p50 %.2f ms p99 %.2f ms" % (summ["solves_per_s"], summ["p50_ms"],
                                                                  summ["p99_ms"]))

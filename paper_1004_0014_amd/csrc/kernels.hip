@@ -94,27 +94,57 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
     }
 }
 
-// out[0..nm) = sums of slots 0..nm-1 over the blocks' records; with
-// extra >= 0 also out[nm] = the sum of slot `extra`.
-__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part, int nblocks,
-                                                 int stride, int nm, int extra,
-                                                 double* __restrict__ out)
+// Sum of the blocks' records: record b is part[b * NS .. b * NS + NS).
+// out[0..nm) = sums of slots 0..nm-1; with extra >= 0 also out[nm] = the sum
+// of slot `extra`.  Thread t loads whole records t, t + 512, ... (NS
+// independent loads each, so the latency is paid once per record, not once
+// per value) and adds them in order; the 512 partial records are then
+// combined in a fixed tree (wave shuffles, then the 8 waves in order):
+// deterministic.
+template <int NS>
+__global__ void __launch_bounds__(512) k_reduce(const double* __restrict__ part, int nblocks, int nm,
+                                                int extra, double* __restrict__ out)
 {
-    // thread (chunk c of 32, moment m of 32): sum of blocks c, c+32, ... in
-    // order, then the 32 chunks in order
-    __shared__ double chunk[32][33];
-    const int m = threadIdx.x & 31, c = threadIdx.x >> 5;
-    const int slot = m < nm ? m : (m == nm ? extra : -1);
-    double s = 0.0;
-    if (slot >= 0)
-        for (int b = c; b < nblocks; b += 32) s += part[(size_t)b * stride + slot];
-    chunk[c][m] = s;
+    __shared__ double wsum[8][NS];
+    double s[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) s[m] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 512) {
+        const double* r = part + (size_t)b * NS;
+        double v[NS];
+#pragma unroll
+        for (int m = 0; m < NS; ++m) v[m] = r[m];
+#pragma unroll
+        for (int m = 0; m < NS; ++m) s[m] += v[m];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const double t = wave_sum(s[m]);
+        if (lane == 0) wsum[wv][m] = t;
+    }
     __syncthreads();
-    if ((int)threadIdx.x < nm + (extra >= 0 ? 1 : 0)) {
-        double t = chunk[0][threadIdx.x];
-        for (int k = 1; k < 32; ++k) t += chunk[k][threadIdx.x];
+    const int nout = nm + (extra >= 0 ? 1 : 0);
+    if ((int)threadIdx.x < nout) {
+        const int slot = (int)threadIdx.x < nm ? (int)threadIdx.x : extra;
+        double t = wsum[0][slot];
+        for (int w = 1; w < 8; ++w) t += wsum[w][slot];
         out[threadIdx.x] = t;
     }
+}
+
+static hipError_t run_reduce(const double* part, int nblocks, int stride, int nm, int extra,
+                             double* out, hipStream_t s)
+{
+    switch (stride) {
+    case 6: k_reduce<6><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
+    case 8: k_reduce<8><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
+    case 9: k_reduce<9><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
+    case 15: k_reduce<15><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
+    case 27: k_reduce<27><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ compose ----
@@ -751,8 +781,18 @@ __global__ void __launch_bounds__(256) k_support(const F* __restrict__ f0, int n
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        atomicMin(&sb[a], lo[a]);
-        atomicMax(&sb[3 + a], hi[a]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&sb[a], lo[a]);
+            atomicMax(&sb[3 + a], hi[a]);
+        }
     }
     __syncthreads();
     if (threadIdx.x < 3) atomicMin(&box[threadIdx.x], sb[threadIdx.x]);
@@ -765,13 +805,18 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_absmax_rows(const S* __restrict__ a, size_t n,
                                                      float* __restrict__ out)
 {
+    __shared__ float wm[4];
     const S* row = a + (size_t)blockIdx.y * n;
     float m = 0.0f;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
         m = fmaxf(m, fabsf(widen<float>(row[i])));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax((int*)&out[blockIdx.y], __float_as_int(m));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    // one atomic per block (few blocks per row: little contention)
+    if (threadIdx.x == 0)
+        atomicMax((int*)&out[blockIdx.y], __float_as_int(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
 }
 
 // ------------------------------------------------- gather backprojection --
@@ -800,9 +845,12 @@ struct BPFoot {
 };
 
 // Pixel box (inclusive, clipped to the detector) that holds every ray
-// meeting the index-space box [lo, hi]; empty (i0 > i1) if none can.
+// meeting the index-space box [lo, hi]: the pixels whose centres lie in the
+// bounding box of the projected corners (the box projects inside their
+// convex hull), widened by `eps` pixels for the FP32 rounding of the
+// projection; empty (i0 > i1) if none can.
 __device__ __forceinline__ void footprint(const BPFoot& F, const float lo[3], const float hi[3],
-                                          int& iu0, int& iu1, int& iv0, int& iv1)
+                                          float eps, int& iu0, int& iu1, int& iv0, int& iv1)
 {
     float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
     bool front = true;
@@ -824,11 +872,10 @@ __device__ __forceinline__ void footprint(const BPFoot& F, const float lo[3], co
         iu0 = 0; iu1 = F.nu - 1; iv0 = 0; iv1 = F.nv - 1;
         return;
     }
-    // one pixel of margin on each side covers the FP32 rounding of the box
-    iu0 = max(0, (int)floorf(fmaxf((umin - F.u0) * F.inv_du, -2.0f)) - 1);
-    iu1 = min(F.nu - 1, (int)ceilf(fminf((umax - F.u0) * F.inv_du, (float)F.nu + 2.0f)) + 1);
-    iv0 = max(0, (int)floorf(fmaxf((vmin - F.v0) * F.inv_dv, -2.0f)) - 1);
-    iv1 = min(F.nv - 1, (int)ceilf(fminf((vmax - F.v0) * F.inv_dv, (float)F.nv + 2.0f)) + 1);
+    iu0 = max(0, (int)ceilf(fmaxf((umin - F.u0) * F.inv_du - eps, -2.0f)));
+    iu1 = min(F.nu - 1, (int)floorf(fminf((umax - F.u0) * F.inv_du + eps, (float)F.nu + 2.0f)));
+    iv0 = max(0, (int)ceilf(fmaxf((vmin - F.v0) * F.inv_dv - eps, -2.0f)));
+    iv1 = min(F.nv - 1, (int)floorf(fminf((vmax - F.v0) * F.inv_dv + eps, (float)F.nv + 2.0f)));
 }
 
 struct BPArgs {
@@ -849,6 +896,9 @@ __global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* _
     __shared__ R s_q[3][256];      // nearest sample to the brick centre, minus the brick origin
     __shared__ R s_d[3][256];      // index-space step per sample
     __shared__ float s_inv[3][256];
+    // slab bounds in samples for the voxel at the brick origin: voxel l
+    // (brick-local) sees samples m in (lo_a + l_a inv_a, hi_a + l_a inv_a)
+    __shared__ float s_lo[3][256], s_hi[3][256];
     __shared__ R s_rw[256];        // r dt
     __shared__ int s_m[2][256];    // valid sample offsets [m0, m1] from that sample
     __shared__ int s_box[4];
@@ -862,13 +912,13 @@ __global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* _
     if (t == 0) {
         const float lo[3] = {(float)(b0[0] - 1), (float)(b0[1] - 1), (float)(b0[2] - 1)};
         const float hi[3] = {(float)(b0[0] + A.bx), (float)(b0[1] + A.by), (float)(b0[2] + A.bz)};
-        footprint(A.F, lo, hi, s_box[0], s_box[1], s_box[2], s_box[3]);
+        footprint(A.F, lo, hi, 1.0f, s_box[0], s_box[1], s_box[2], s_box[3]);
     }
     int ru0 = 0, ru1 = -1, rv0 = 0, rv1 = -1;
     if (inside) {
         const float lo[3] = {(float)(v[0] - 1), (float)(v[1] - 1), (float)(v[2] - 1)};
         const float hi[3] = {(float)(v[0] + 1), (float)(v[1] + 1), (float)(v[2] + 1)};
-        footprint(A.F, lo, hi, ru0, ru1, rv0, rv1);
+        footprint(A.F, lo, hi, 0.02f, ru0, ru1, rv0, rv1);
     }
     __syncthreads();
     const int bu0 = s_box[0], bu1 = s_box[1], bv0 = s_box[2], bv1 = s_box[3];
@@ -920,7 +970,11 @@ __global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* _
                     s_q[ax][t] = (R)qr[ax];
                     s_d[ax][t] = (R)dq[ax];
                     const float df = (float)dq[ax];
-                    s_inv[ax][t] = fabsf(df) > 1e-30f ? 1.0f / df : 1.0e30f;
+                    const float inv = fabsf(df) > 1e-30f ? 1.0f / df : 1.0e30f;
+                    const float e1 = (-1.0f - (float)qr[ax]) * inv, e2 = (1.0f - (float)qr[ax]) * inv;
+                    s_inv[ax][t] = inv;
+                    s_lo[ax][t] = fminf(e1, e2);
+                    s_hi[ax][t] = fmaxf(e1, e2);
                 }
                 s_rw[t] = rw;
                 s_m[0][t] = m0;
@@ -932,23 +986,22 @@ __global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* _
             for (int iv = va; iv <= vb; ++iv) {
                 for (int iu = ua; iu <= ub; ++iu) {
                     const int k = ((iv - tv0) << 4) + (iu - tu0);
+                    // samples m with |q_m - l| < 1 on every axis (slab test;
+                    // the 1e-3 sample slack covers the FP32 rounding of the
+                    // bounds, and the weights clip any sample it admits)
+                    const float lx = (float)l[0], ly = (float)l[1], lz = (float)l[2];
+                    const float ix = s_inv[0][k], iy = s_inv[1][k], iz = s_inv[2][k];
+                    float lo = fmaxf(fmaxf(fmaf(lx, ix, s_lo[0][k]), fmaf(ly, iy, s_lo[1][k])),
+                                     fmaf(lz, iz, s_lo[2][k]));
+                    float hi = fminf(fminf(fmaf(lx, ix, s_hi[0][k]), fmaf(ly, iy, s_hi[1][k])),
+                                     fmaf(lz, iz, s_hi[2][k]));
+                    lo = fminf(fmaxf(lo, -1.0e6f), 1.0e6f);   // |m| stays far inside int range
+                    hi = fminf(fmaxf(hi, -1.0e6f), 1.0e6f);
+                    const int m0 = max(s_m[0][k], (int)ceilf(lo - 1.0e-3f));
+                    const int m1 = min(s_m[1][k], (int)floorf(hi + 1.0e-3f));
+                    if (m0 > m1) continue;
                     const R rx = s_q[0][k] - lr[0], ry = s_q[1][k] - lr[1], rz = s_q[2][k] - lr[2];
                     const R dx = s_d[0][k], dy = s_d[1][k], dz = s_d[2][k];
-                    // samples m with |r + m d| < 1 on every axis (slab test,
-                    // widened to whole samples; the weights clip the rest)
-                    float lo = -1.0e6f, hi = 1.0e6f;
-                    {
-                        const float ix = s_inv[0][k], iy = s_inv[1][k], iz = s_inv[2][k];
-                        const float ex1 = (-1.0f - (float)rx) * ix, ex2 = (1.0f - (float)rx) * ix;
-                        const float ey1 = (-1.0f - (float)ry) * iy, ey2 = (1.0f - (float)ry) * iy;
-                        const float ez1 = (-1.0f - (float)rz) * iz, ez2 = (1.0f - (float)rz) * iz;
-                        lo = fmaxf(lo, fmaxf(fminf(ex1, ex2), fmaxf(fminf(ey1, ey2), fminf(ez1, ez2))));
-                        hi = fminf(hi, fminf(fmaxf(ex1, ex2), fminf(fmaxf(ey1, ey2), fmaxf(ez1, ez2))));
-                    }
-                    lo = fminf(lo, 1.0e6f);    // |m| stays far inside int range
-                    hi = fmaxf(hi, -1.0e6f);
-                    const int m0 = max(s_m[0][k], (int)floorf(lo));
-                    const int m1 = min(s_m[1][k], (int)ceilf(hi));
                     const R rw = s_rw[k];
                     for (int m = m0; m <= m1; ++m) {
                         const R fm = (R)m;
@@ -1412,8 +1465,7 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     if (moments) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_reduce<<<1, 1024, 0, s>>>(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C),
-                                moments);
+        return run_reduce(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C), moments, s);
     }
     return hipGetLastError();
 }
@@ -1462,9 +1514,7 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
 #undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
-    k_reduce<<<1, 1024, 0, s>>>(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C),
-                                moments);
-    return hipGetLastError();
+    return run_reduce(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C), moments, s);
 }
 
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
@@ -1481,8 +1531,7 @@ hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const Ray
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
                          hipStream_t s)
 {
-    k_reduce<<<1, 1024, 0, s>>>(partials, nblocks, stride, nm, -1, out);
-    return hipGetLastError();
+    return run_reduce(partials, nblocks, stride, nm, -1, out, s);
 }
 
 hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeom& rg,
@@ -1574,8 +1623,8 @@ hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0,
                           hipStream_t s)
 {
     const long nxy = (long)g.n[0] * g.n[1];
-    const unsigned bx = (unsigned)std::min<long>((nxy + 255) / 256, 64);
-    const unsigned bz = (unsigned)std::min(g.n[2], 256);
+    const unsigned bx = (unsigned)std::min<long>((nxy + 255) / 256, 16);
+    const unsigned bz = (unsigned)std::min(g.n[2], 64);
     PCR_DISPATCH_S(f0_dtype, F,
         k_support<F><<<dim3(bx, bz), 256, 0, s>>>((const F*)f0, g.n[0], g.n[1], g.n[2], box));
     return hipGetLastError();
@@ -1584,7 +1633,7 @@ hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0,
 hipError_t launch_absmax_rows(pcr_dtype dt, const void* a, size_t n, int rows, float* out,
                               hipStream_t s)
 {
-    const unsigned bx = (unsigned)std::min<size_t>((n + 255) / 256, 512);
+    const unsigned bx = (unsigned)std::min<size_t>((n + 1023) / 1024, 256);
     PCR_DISPATCH_S(dt, S,
         k_absmax_rows<S><<<dim3(bx, (unsigned)rows), 256, 0, s>>>((const S*)a, n, out));
     return hipGetLastError();

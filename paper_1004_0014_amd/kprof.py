@@ -24,7 +24,7 @@ COPY_BYTES = 256 << 20
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", default="c1")
+    ap.add_argument("--config", default="paper")
     ap.add_argument("--angle", type=float, default=30.0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward"])

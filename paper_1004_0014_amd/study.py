@@ -58,7 +58,7 @@ def rel_err(a, b):
     return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
 
 
-def run_rotation(name="c1", every=1, nu=None, dev="cuda"):
+def run_rotation(name="paper", every=1, nu=None, dev="cuda"):
     cfg = S.config(name)
     g = S.grid_for(name)
     K = cfg["K"]
@@ -103,7 +103,7 @@ def run_rotation(name="c1", every=1, nu=None, dev="cuda"):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", default="c1")
+    ap.add_argument("--config", default="paper")
     ap.add_argument("--every", type=int, default=10, help="use every n-th projection (degree)")
     ap.add_argument("--resolutions", default="", help="comma list of detector widths (pixels)")
     ap.add_argument("--rows", action="store_true", help="print per-projection rows")

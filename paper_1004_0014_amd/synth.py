@@ -281,17 +281,17 @@ def truth_w(model: PCAModel, phi: float, scale: float = 1.5):
 # ------------------------------------------------------------- configs ----
 CONFIGS = {
     # tiny FP64 case: 64^3 at 4 mm, 128x96 detector at 1.6 mm, 30 deg
-    "c0": dict(n=(64, 64, 64), spacing=(4.0, 4.0, 4.0), K=3, nu=128, nv=96,
+    "tiny": dict(n=(64, 64, 64), spacing=(4.0, 4.0, 4.0), K=3, nu=128, nv=96,
                du=1.6, dv=1.6, step=2.0, angles=[math.radians(30.0)], max_iter=30),
     # paper-scale FP32: 256x256x100 at 1.875x1.875x2.5 mm, 512x384 at 0.776 mm
-    "c1": dict(n=(256, 256, 100), spacing=(1.875, 1.875, 2.5), K=3, nu=512, nv=384,
+    "paper": dict(n=(256, 256, 100), spacing=(1.875, 1.875, 2.5), K=3, nu=512, nv=384,
                du=0.776, dv=0.776, step=0.9375,
                angles=[math.radians(i) for i in range(360)], rate_hz=11.0, max_iter=50),
     # differentiation: 128^3 at 3 mm, 256x192 at 1.552 mm, K in {3, 5}
-    "c2": dict(n=(128, 128, 128), spacing=(3.0, 3.0, 3.0), K=3, nu=256, nv=192,
+    "diff": dict(n=(128, 128, 128), spacing=(3.0, 3.0, 3.0), K=3, nu=256, nv=192,
                du=1.552, dv=1.552, step=1.5, n_angles=8, angle_seed=2),
     # precision: 256x256x128, K = 4, 16-bit storage
-    "c3": dict(n=(256, 256, 128), spacing=(1.875, 1.875, 2.5), K=4, nu=512, nv=384,
+    "precision": dict(n=(256, 256, 128), spacing=(1.875, 1.875, 2.5), K=4, nu=512, nv=384,
                du=0.776, dv=0.776, step=0.9375,
                angles=[math.radians(i) for i in range(360)], rate_hz=11.0, max_iter=50),
 }
@@ -299,7 +299,7 @@ CONFIGS = {
 
 def config(name: str) -> dict:
     cfg = dict(CONFIGS[name])
-    if name == "c2":
+    if name == "diff":
         rng = np.random.default_rng(cfg["angle_seed"])
         cfg["angles"] = list(rng.uniform(0, 2 * np.pi, cfg["n_angles"]))
     return cfg

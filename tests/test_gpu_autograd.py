@@ -40,26 +40,26 @@ def test_gradcheck_fp64_small():
 
 
 @pytest.fixture(scope="module", params=[3, 5])
-def c2(request):
+def diff_case(request):
     K = request.param
-    cfg = S.config("c2")
-    g = S.grid_for("c2")
+    cfg = S.config("diff")
+    g = S.grid_for("diff")
     m = S.pca_model(g, K)
     return dict(K=K, g=g, m=m, f0=S.phantom(g), angles=cfg["angles"], cfg=cfg)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_autograd_matches_oracle_gradient(c2, dtype):
+def test_autograd_matches_oracle_gradient(diff_case, dtype):
     L, A = _mods()
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    g, m, K = c2["g"], c2["m"], c2["K"]
-    f0_t, f0 = rounded(c2["f0"], tdt)
+    g, m, K = diff_case["g"], diff_case["m"], diff_case["K"]
+    f0_t, f0 = rounded(diff_case["f0"], tdt)
     mean_t, mean = rounded(m.mean, tdt)
     U_t, U = rounded(m.U, tdt)
     dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV))
-    angles = c2["angles"] if dtype == "f64" else c2["angles"][:4]
+    angles = diff_case["angles"] if dtype == "f64" else diff_case["angles"][:4]
     for j, ang in enumerate(angles):
-        G = S.geom_for("c2", ang)
+        G = S.geom_for("diff", ang)
         w_true = S.truth_w(m, 0.4 + 0.7 * j)
         y = oracle.project(g, G, oracle.warp(g, f0, oracle.compose(g, mean, U, w_true)))
         w0 = w_true * 0.8 + 5.0
@@ -79,13 +79,13 @@ def test_autograd_matches_oracle_gradient(c2, dtype):
         assert rel_l2(f0d.grad.cpu().numpy(), gf0) <= tol_f, ang
 
 
-def test_autograd_matches_central_fd(c2):
+def test_autograd_matches_central_fd(diff_case):
     L, A = _mods()
-    g, m, K = c2["g"], c2["m"], c2["K"]
-    f0_t, f0 = rounded(c2["f0"], torch.float64)
+    g, m, K = diff_case["g"], diff_case["m"], diff_case["K"]
+    f0_t, f0 = rounded(diff_case["f0"], torch.float64)
     dm = L.DeviceModel(torch.tensor(m.mean, dtype=torch.float64, device=DEV),
                        torch.tensor(m.U, dtype=torch.float64, device=DEV))
-    G = S.geom_for("c2", c2["angles"][0])
+    G = S.geom_for("diff", diff_case["angles"][0])
     w_true = S.truth_w(m, 2.2)
     f0d = f0_t.to(DEV)
     with torch.no_grad():
@@ -111,8 +111,8 @@ def test_autograd_matches_central_fd(c2):
 def test_adjoint_dot_products_seeded(dtype):
     L, _ = _mods()
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    g = S.grid_for("c2")
-    G = S.geom_for("c2", S.config("c2")["angles"][3])
+    g = S.grid_for("diff")
+    G = S.geom_for("diff", S.config("diff")["angles"][3])
     rng = np.random.default_rng(3)
     x = torch.tensor(rng.standard_normal(g.shape), dtype=tdt, device=DEV)
     yv = torch.tensor(rng.standard_normal((G.nv, G.nu)), dtype=tdt, device=DEV)

@@ -166,15 +166,15 @@ def test_warp_adjoint_parity():
 
 # ------------------------------------------------------- cost / gradient ---
 @pytest.fixture(scope="module")
-def c0case():
-    g = S.grid_for("c0")
-    return Case(g, S.geom_for("c0"), K=3, phi=2.0).device(DEV)
+def tiny_case():
+    g = S.grid_for("tiny")
+    return Case(g, S.geom_for("tiny"), K=3, phi=2.0).device(DEV)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_cost_grad_parity(c0case, mode):
+def test_cost_grad_parity(tiny_case, mode):
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     y = torch.tensor(c.y, dtype=torch.float32, device=DEV)
     for w, a, b in [(0.5 * c.w_true, 1.0, 0.0), (np.array([100.0, -50.0, 30.0]), 0.9, 0.05)]:
@@ -185,11 +185,11 @@ def test_cost_grad_parity(c0case, mode):
     ctx.close()
 
 
-def test_cost_grad_across_layouts(c0case):
+def test_cost_grad_across_layouts(tiny_case):
     """The fused image switches between x- and y-fastest storage with the
     gantry angle; every angle must agree with the oracle."""
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     w = 0.6 * c.w_true
     for ang in (30.0, 100.0, 200.0, 290.0, 44.0, 136.0):
@@ -204,9 +204,9 @@ def test_cost_grad_across_layouts(c0case):
     ctx.close()
 
 
-def test_cost_grad_fp64_compute(c0case):
+def test_cost_grad_fp64_compute(tiny_case):
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0, compute=torch.float64)
     y = torch.tensor(c.y, dtype=torch.float64, device=DEV)
     w = 0.7 * c.w_true
@@ -218,9 +218,9 @@ def test_cost_grad_fp64_compute(c0case):
     ctx.close()
 
 
-def test_cost_grad_deterministic(c0case):
+def test_cost_grad_deterministic(tiny_case):
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     y = torch.tensor(c.y, dtype=torch.float32, device=DEV)
     r1 = ctx.cost_grad(y, c.geom, 0.3 * c.w_true, 1.0, 0.0)
@@ -231,11 +231,11 @@ def test_cost_grad_deterministic(c0case):
 
 # -------------------------------------------------------------- solver ----
 @pytest.mark.parametrize("mode", [0, 1])
-def test_solve_parity_tiny_config(c0case, mode):
+def test_solve_parity_tiny_config(tiny_case, mode):
     """30 Armijo iterations from w = 0 (tiny configuration): final w within
     1e-3 of the oracle's; (a, b) and J agree."""
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     y = torch.tensor(c.y, dtype=torch.float32, device=DEV)
     opts = L.default_opts(max_iter=30, step0=c.step0, grad_mode=mode)
@@ -248,9 +248,9 @@ def test_solve_parity_tiny_config(c0case, mode):
     ctx.close()
 
 
-def test_fixed_step_trajectory_parity(c0case):
+def test_fixed_step_trajectory_parity(tiny_case):
     L = _lib()
-    c = c0case
+    c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     y = torch.tensor(c.y, dtype=torch.float32, device=DEV)
     for iters in (1, 3, 6):

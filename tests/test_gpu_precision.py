@@ -99,3 +99,25 @@ def test_solve_and_tumour_16bit(case, storage):
     assert np.linalg.norm(np.array(s16["tumor_mm"]) - pt) <= 0.1
     # leading coefficients agree with the FP32 path to the storage precision
     assert abs(w16[0] - w32[0]) <= 1e-2 * abs(w32[0])
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_cost_grad_16bit_fused_image(case, storage):
+    """With 16-bit storage the fused image (f and the tangents) is held in
+    FP16 scaled by powers of two; J and dJ/dw against the oracle fed the same
+    rounded model and image agree to that rounding (FP16: 2^-11 relative per
+    stored value), far below the 1e-2 target."""
+    L = _L()
+    g, G, m = case["g"], case["G"], case["m"]
+    dm, f0d, r = _model(case, storage)
+    w_true = S.truth_w(m, 1.2)
+    y_np = oracle.project(g, G, oracle.warp(g, r["f0"], oracle.compose(g, r["mean"], r["U"], w_true)))
+    y = torch.tensor(y_np, dtype=torch.float32, device=DEV)
+    y_np = y.double().cpu().numpy()
+    ctx = L.Context(g, dm, f0d)
+    for w in (0.4 * w_true, 1.3 * w_true):
+        J, grad = ctx.cost_grad(y, G, w, 1.05, 0.01)
+        Jo, go = oracle.cost_grad(g, G, r["f0"], r["mean"], r["U"], w, y_np, 1.05, 0.01)
+        assert abs(J - Jo) <= 2e-3 * Jo, (J, Jo)
+        assert rel_l2(grad, go) <= 1e-2, (grad, go)
+    ctx.close()

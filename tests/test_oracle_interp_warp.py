@@ -76,7 +76,7 @@ def test_compose_is_mean_plus_Uw():
 
 
 def test_identity_warp_is_bitwise():
-    g = S.grid_for("c0")
+    g = S.grid_for("tiny")
     f0 = S.phantom(g)
     f = oracle.warp(g, f0, np.zeros((3,) + g.shape))
     assert np.array_equal(f, f0)

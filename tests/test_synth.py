@@ -39,7 +39,7 @@ def test_test_motion_lies_in_model_span():
 
 
 def test_phantom_deterministic_and_bounded():
-    g = S.grid_for("c0")
+    g = S.grid_for("tiny")
     a = S.phantom(g, seed=0)
     b = S.phantom(g, seed=0)
     assert np.array_equal(a, b)
