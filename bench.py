@@ -159,14 +159,16 @@ def storage_model(W, storage, dev):
     return _lib.DeviceModel(mean, U, scale=scale), f0
 
 
-def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order=0, hist=None):
+def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order=0, hist=None,
+                 chain_mu=False):
     """Solves the projections in order, each warm-started from the previous
     result, or with predict_order > 0 from the polynomial extrapolation of
     the last results to the frame's time (the prediction is inside the timed
-    solve).  `hist` is a list of (t, w) carried across calls."""
+    solve).  `hist` is a list of (t, w) carried across calls.  With chain_mu
+    each solve's first trial uses the step size the previous solve ended with."""
     import torch
     from paper_1004_0014_amd import _lib
-    lat, iters, trials, werr, terr, evals, samples = [], [], [], [], [], [], []
+    lat, iters, trials, werr, terr, evals, samples, ends = [], [], [], [], [], [], [], []
     w = list(w0)
     hist = [] if hist is None else hist
     torch.cuda.synchronize()
@@ -181,6 +183,8 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
             w = _lib.predict_w([h[1] for h in last], [h[0] for h in last], t_i, predict_order)
         w, ab, st = ctx.reconstruct(y, G, w, opts)
         lat.append(time.perf_counter() - t0)
+        if chain_mu:
+            opts.mu0 = st["mu"]
         hist.append((t_i, list(w)))
         if (n + 1) % 60 == 0:
             log("[bench]   %d solves, last %.2f ms, %d iterations" % (n + 1, 1e3 * lat[-1],
@@ -189,6 +193,9 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
         trials.append(st["trials"])
         evals.append(st["trials"] + 1)
         samples.append(st["samples"])
+        # how the solve ended: tolerance met, iteration cap, line search exhausted
+        ends.append("tol" if st["status"] == 0 else
+                    ("cap" if st["iterations"] >= opts.max_iter else "armijo"))
         _, _, phi, wt = W.frame(i)
         werr.append(float(np.linalg.norm(np.array(w) - wt) / np.linalg.norm(wt)))
         terr.append(st["tumor_mm"])
@@ -198,7 +205,7 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
     if profile:
         _lib.profile_enable(False)
     return dict(lat=np.array(lat), iters=np.array(iters), trials=np.array(trials),
-                evals=np.array(evals), samples=np.array(samples), werr=np.array(werr),
+                evals=np.array(evals), samples=np.array(samples), ends=ends, werr=np.array(werr),
                 tumor=np.array(terr), w=w,
                 elapsed=elapsed, prof=prof, hist=hist)
 
@@ -223,6 +230,7 @@ def summarise(res, W, idxs, samples_per_proj):
         "ray_samples_per_s": marched / res["elapsed"],
         "ray_samples_per_s_support_box": samples / res["elapsed"],
         "marched_fraction": marched / samples,
+        "solve_end": {k: res["ends"].count(k) for k in ("tol", "cap", "armijo")},
         "w_rel_err_vs_truth_median": float(np.median(res["werr"])),
         "w_rel_err_vs_truth_max": float(np.max(res["werr"])),
         "tumour_err_mm_mean": float(np.mean(tumour_err)),
@@ -325,7 +333,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
-    ap.add_argument("--variants", default="bf16,adjoint,predict,fluoro,fluoro-predict",
+    ap.add_argument("--variants", default="bf16,f16,adjoint,chain,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
     ap.add_argument("--variant-steps", type=int, default=0,
                     help="steps of each variant (0: as many as the main run; the adjoint "
@@ -377,7 +385,7 @@ def main():
         "ray_samples_per_s": summ["ray_samples_per_s"],
         "accuracy": {k: summ[k] for k in ("w_rel_err_vs_truth_median", "w_rel_err_vs_truth_max",
                                           "tumour_err_mm_mean", "tumour_err_mm_max",
-                                          "mean_iterations", "mean_trials")},
+                                          "mean_iterations", "mean_trials", "solve_end")},
         "kernels": kernel_table(res["prof"]),
         "roofline": roofline(W, res["prof"],
                              float(np.sum(res["samples"])) / max(res["prof"]["march"][1], 1), channels,
@@ -404,19 +412,22 @@ def main():
             wv = run_sequence(ctx, W, ys[:Wm], geoms[:Wm], idxs[:Wm], o2, [0.0] * K)
             rv = run_sequence(ctx, W, ys[Wm:Wm + vsteps], geoms[Wm:Wm + vsteps],
                               idxs[Wm:Wm + vsteps], o2, wv["w"], profile=True)
-        elif v in ("predict", "fluoro", "fluoro-predict"):
-            po = args.predict_order if v.endswith("predict") else 0
+        elif v in ("predict", "fluoro", "fluoro-predict", "chain", "predict-chain"):
+            po = args.predict_order if "predict" in v else 0
+            chain = v.endswith("chain")
+            vo = _lib.default_opts(max_iter=W.cfg["max_iter"], step0=W.model.step0, grad_mode=mode,
+                                   localize=1, p_ref_mm=W.p_ref)
             if v.startswith("fluoro"):
                 if fl is None:
                     fl = W.measurements(idxs[:Wm + vsteps], fixed_angle=math.radians(args.fluoro_angle))
                 vy, vg = fl
             else:
                 vy, vg = ys, geoms
-            wv = run_sequence(ctx, W, vy[:Wm], vg[:Wm], idxs[:Wm], opts, [0.0] * K,
-                              predict_order=po)
+            wv = run_sequence(ctx, W, vy[:Wm], vg[:Wm], idxs[:Wm], vo, [0.0] * K,
+                              predict_order=po, chain_mu=chain)
             rv = run_sequence(ctx, W, vy[Wm:Wm + vsteps], vg[Wm:Wm + vsteps],
-                              idxs[Wm:Wm + vsteps], opts, wv["w"], profile=True,
-                              predict_order=po, hist=wv["hist"])
+                              idxs[Wm:Wm + vsteps], vo, wv["w"], profile=True,
+                              predict_order=po, hist=wv["hist"], chain_mu=chain)
             if v.startswith("fluoro"):
                 vspp = np.full(vsteps, float(samples_per_ray(W.grid, vg[Wm]).sum()))
         else:
@@ -426,6 +437,8 @@ def main():
             sv["angle_deg"] = args.fluoro_angle
         if po:
             sv["predict_order"] = po
+        if v.endswith("chain"):
+            sv["step_size_carried"] = True
         sv["steps"] = vsteps
         sv["kernels"] = kernel_table(rv["prof"])
         variants[v] = sv

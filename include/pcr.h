@@ -125,6 +125,10 @@ typedef struct pcr_solve_opts {
     double p_ref_mm[3];      /* tumour position in the reference image */
     double fp_tol_mm;        /* fixed-point stop: update shorter than this (1e-6) */
     int32_t fp_max_iter;     /* fixed-point iteration cap (200) */
+    double mu0;              /* > 0: step size of the solve's first trial instead of
+                                step0 / |g_0| -- e.g. the `mu` a previous frame's solve
+                                returned, which carries the line search's scale across
+                                warm-started frames (default 0) */
 } pcr_solve_opts;
 
 typedef struct pcr_solve_stats {
@@ -140,6 +144,7 @@ typedef struct pcr_solve_stats {
     double samples;          /* ray samples marched over all projections of the solve
                                 (rays are clipped to the box where the warped image
                                 can be nonzero, so this is the work done) */
+    double mu;               /* step size the next iteration would have tried first */
 } pcr_solve_stats;
 
 typedef struct pcr_ctx pcr_ctx;
@@ -289,6 +294,8 @@ typedef struct pcr_server_opts {
     int32_t predict_order;    /* warm start of each solve: 0 = the stream's previous
                                  result; 1, 2 = pcr_predict_w over the stream's last
                                  results at their submit times */
+    int32_t chain_step;       /* nonzero: each solve's first trial uses the step size
+                                 the stream's previous solve ended with (opts.mu0) */
 } pcr_server_opts;
 
 typedef struct pcr_result {
@@ -301,6 +308,8 @@ typedef struct pcr_result {
     double w[8];              /* result */
     double ab[2], J, tumor_mm[3];
     double t_submit_s, t_start_s, t_done_s;   /* steady-clock seconds */
+    double mu0, mu;           /* step size of the first trial, and the one the solve
+                                 ended with (see pcr_solve_opts.mu0) */
 } pcr_result;
 
 /* Creates the server and its worker thread on the current device. */

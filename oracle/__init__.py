@@ -48,13 +48,13 @@ class _Geom(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("max_backtracks", C.c_int), ("sigma", C.c_double),
                 ("beta", C.c_double), ("eps_g", C.c_double), ("step0", C.c_double),
-                ("fixed_mu", C.c_double)]
+                ("fixed_mu", C.c_double), ("mu0", C.c_double)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("trials", C.c_int), ("status", C.c_int),
                 ("J0", C.c_double), ("J", C.c_double), ("gnorm0", C.c_double),
-                ("gnorm", C.c_double), ("a", C.c_double), ("b", C.c_double)]
+                ("gnorm", C.c_double), ("a", C.c_double), ("b", C.c_double), ("mu", C.c_double)]
 
 
 _lib = None
@@ -251,6 +251,7 @@ class SolveOpts:
     eps_g: float = 1e-4
     step0: float = 1.0
     fixed_mu: float = 0.0
+    mu0: float = 0.0
 
 
 def solve(grid, geom, f0, mean, U, y, w0, opts: SolveOpts):
@@ -263,7 +264,7 @@ def solve(grid, geom, f0, mean, U, y, w0, opts: SolveOpts):
     w = np.array(w0, dtype=np.float64, copy=True)
     ab = np.zeros(2)
     o = _Opts(opts.max_iter, opts.max_backtracks, opts.sigma, opts.beta, opts.eps_g,
-              opts.step0, opts.fixed_mu)
+              opts.step0, opts.fixed_mu, opts.mu0)
     st = _Stats()
     Jh = np.full(opts.max_iter + 1, np.nan)
     _load().orc_solve(C.byref(_grid(grid)), C.byref(_geom(geom)), _p(f0), K, _p(mean), _p(U),

@@ -444,7 +444,9 @@ static double next_initial_step(double J, double g2, double Jt, double mu_acc, d
  * silent: (a, b) start with step 2 at w_0; step 1 is gradient descent on w
  * with a, b fixed and the step from Armijo's rule: trial w - mu g accepted
  * when J' <= J - sigma mu |g|^2 (ties accept), otherwise mu <- beta mu for at
- * most max_backtracks trials; the first trial of a solve moves w by step0;
+ * most max_backtracks trials; the first trial of a solve moves w by step0
+ * (or uses the given step size mu0, e.g. carried over from the previous
+ * frame's solve);
  * each later iteration's first trial is the minimiser of the quadratic in mu
  * that matches the previous iteration's line (its J, its slope -|g|^2 and the
  * accepted trial's J'), kept within [beta mu', mu'/beta] of the accepted mu'
@@ -469,7 +471,7 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
     double J = orc_cost_grad(g, G, f0, K, mean, U, w, y, ab[0], ab[1], grad, NULL);
     double gn = norm(K, grad), g0 = gn, J0 = J;
     if (J_hist) J_hist[0] = J;
-    double mu = o->fixed_mu > 0 ? o->fixed_mu : (g0 > 0 ? o->step0 / g0 : 0.0);
+    double mu = o->fixed_mu > 0 ? o->fixed_mu : (o->mu0 > 0 ? o->mu0 : (g0 > 0 ? o->step0 / g0 : 0.0));
 
     for (int n = 0;; ++n) {
         if (gn <= o->eps_g * g0) break;
@@ -506,6 +508,7 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
         st->iterations = iters; st->trials = trials; st->status = status;
         st->J0 = J0; st->J = J; st->gnorm0 = g0; st->gnorm = gn;
         st->a = ab[0]; st->b = ab[1];
+        st->mu = mu;
     }
     free(p); free(grad); free(wt);
     return status;

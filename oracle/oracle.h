@@ -47,11 +47,13 @@ typedef struct {
     double eps_g;         /* stop when |g_n| <= eps_g |g_0| */
     double step0;         /* first trial moves w by this distance */
     double fixed_mu;      /* > 0: constant step, no line search */
+    double mu0;           /* > 0: step size of the first trial (else step0 / |g_0|) */
 } orc_opts;
 
 typedef struct {
     int iterations, trials, status;
     double J0, J, gnorm0, gnorm, a, b;
+    double mu;            /* step size the next iteration would try first */
 } orc_stats;
 
 int orc_num_threads(void);

@@ -48,7 +48,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("max_backtracks", C.c_int32), ("sigma", C.c_double),
                 ("beta", C.c_double), ("eps_g", C.c_double), ("step0", C.c_double),
                 ("fixed_mu", C.c_double), ("grad_mode", C.c_int32), ("localize", C.c_int32),
-                ("p_ref_mm", C.c_double * 3), ("fp_tol_mm", C.c_double), ("fp_max_iter", C.c_int32)]
+                ("p_ref_mm", C.c_double * 3), ("fp_tol_mm", C.c_double), ("fp_max_iter", C.c_int32),
+                ("mu0", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -56,7 +57,7 @@ class SolveStats(C.Structure):
                 ("fp_iterations", C.c_int32), ("fp_status", C.c_int32), ("J0", C.c_double),
                 ("J", C.c_double), ("gnorm0", C.c_double), ("gnorm", C.c_double),
                 ("a", C.c_double), ("b", C.c_double), ("tumor_mm", C.c_double * 3),
-                ("samples", C.c_double)]
+                ("samples", C.c_double), ("mu", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,7 +67,7 @@ class SolveStats(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32),
-                ("predict_order", C.c_int32)]
+                ("predict_order", C.c_int32), ("chain_step", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -74,7 +75,8 @@ class Result(C.Structure):
                 ("iterations", C.c_int32), ("trials", C.c_int32), ("K", C.c_int32),
                 ("fp_status", C.c_int32), ("w0", C.c_double * 8), ("w", C.c_double * 8),
                 ("ab", C.c_double * 2), ("J", C.c_double), ("tumor_mm", C.c_double * 3),
-                ("t_submit_s", C.c_double), ("t_start_s", C.c_double), ("t_done_s", C.c_double)]
+                ("t_submit_s", C.c_double), ("t_start_s", C.c_double), ("t_done_s", C.c_double),
+                ("mu0", C.c_double), ("mu", C.c_double)]
 
     def as_dict(self):
         K = self.K
@@ -82,7 +84,8 @@ class Result(C.Structure):
                 "iterations": self.iterations, "trials": self.trials, "fp_status": self.fp_status,
                 "w0": list(self.w0[:K]), "w": list(self.w[:K]), "ab": list(self.ab), "J": self.J,
                 "tumor_mm": list(self.tumor_mm), "t_submit_s": self.t_submit_s,
-                "t_start_s": self.t_start_s, "t_done_s": self.t_done_s}
+                "t_start_s": self.t_start_s, "t_done_s": self.t_done_s, "mu0": self.mu0,
+                "mu": self.mu}
 
 
 _lib = None
@@ -387,8 +390,9 @@ class Server:
     into server-owned device memory at add_stream."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True,
-                 predict_order: int = 0):
-        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0, int(predict_order))
+                 predict_order: int = 0, chain_step: bool = False):
+        o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0, int(predict_order),
+                       1 if chain_step else 0)
         h = C.c_void_p()
         _check(lib().pcr_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -122,6 +122,7 @@ pcr_status check_opts(const pcr_solve_opts* o)
     if (!(o->beta > 0 && o->beta < 1)) return fail(PCR_EINVAL, "beta must be in (0, 1)");
     if (!(o->eps_g >= 0) || !std::isfinite(o->eps_g)) return fail(PCR_EINVAL, "bad eps_g");
     if (!(o->fixed_mu >= 0) || !std::isfinite(o->fixed_mu)) return fail(PCR_EINVAL, "bad fixed_mu");
+    if (!(o->mu0 >= 0) || !std::isfinite(o->mu0)) return fail(PCR_EINVAL, "bad mu0");
     if (o->fixed_mu == 0 && !(o->step0 > 0 && std::isfinite(o->step0)))
         return fail(PCR_EINVAL, "step0 must be > 0");
     if (o->grad_mode != PCR_GRAD_FUSED && o->grad_mode != PCR_GRAD_ADJOINT)
@@ -280,7 +281,7 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     }
     sc->L1 = make_pad(*grid, 1);
     rgc = make_ray_geom(*grid, G, yfast);
-    msc = choose_march_shape(rgc);
+    msc = choose_march_shape(rgc, yfast);
     blocksc = march_blocks(rgc, msc);
     const int dev = sc->device;
     if (mode == PCR_GRAD_FUSED) {

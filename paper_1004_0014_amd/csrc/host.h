@@ -269,7 +269,7 @@ inline pcr_status SolveSM::feed(const Moments& mo, GradFn&& grad_fn)
         PCR_TRY(gradient(w));
         g0 = gn;
         J0 = J;
-        mu = fixed ? o.fixed_mu : (g0 > 0 ? o.step0 / g0 : 0.0);
+        mu = fixed ? o.fixed_mu : (o.mu0 > 0 ? o.mu0 : (g0 > 0 ? o.step0 / g0 : 0.0));
         advance();
         return PCR_OK;
     }
@@ -331,6 +331,7 @@ inline void SolveSM::fill_stats(pcr_solve_stats* st) const
     st->a = a;
     st->b = b;
     st->samples = samples;
+    st->mu = mu;
     st->fp_status = PCR_OK;
 }
 

@@ -1226,7 +1226,17 @@ PadLayout make_pad(const pcr_grid& g, int C, bool yfast)
 
 bool prefer_yfast(const pcr_geom& G)
 {
-    return std::fabs(std::sin(G.angle_rad)) > std::fabs(std::cos(G.angle_rad));
+    // tuning override (layout sweeps): PCR_MARCH_LAYOUT = 1 x-fastest, 2 y-fastest
+    if (const char* e = std::getenv("PCR_MARCH_LAYOUT")) {
+        const int v = std::atoi(e);
+        if (v == 1) return false;
+        if (v == 2) return true;
+    }
+    // Measured on the paper-scale volume: the x-fastest layout with compact
+    // ray tiles is fastest at every angle except within ~15 degrees of the y
+    // axis (rays along x), where the y-fastest layout with one thread per ray
+    // gains ~10 %.
+    return std::fabs(std::sin(G.angle_rad)) > 0.97;
 }
 
 RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
@@ -1266,13 +1276,21 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
     return r;
 }
 
-MarchShape choose_march_shape(const RayGeom& rg)
+MarchShape choose_march_shape(const RayGeom& rg, bool yfast)
 {
     MarchShape ms;
-    ms.tile_u = 16;
     long rays = (long)rg.nu * rg.nv;
-    // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays when they are few
-    ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
+    if (yfast) {
+        // rays close to the x axis on the y-fastest layout: one thread per ray
+        ms.seg = 1;
+        ms.tile_u = 16;
+    } else {
+        // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays when they
+        // are few; tiles of 64 rays per wave as close to square in the volume
+        // as the split allows (4 x 16 with 4 segments, 8 x 8 with 2)
+        ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
+        ms.tile_u = ms.seg == 4 ? 4 : (ms.seg == 2 ? 8 : 16);
+    }
     // tuning overrides (launch-shape sweeps): PCR_MARCH_TILE_U in {4..64},
     // PCR_MARCH_SEG in {1, 2, 4}
     if (const char* e = std::getenv("PCR_MARCH_TILE_U")) {

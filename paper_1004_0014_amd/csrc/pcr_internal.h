@@ -45,7 +45,8 @@ struct PadLayout {
     }
 };
 PadLayout make_pad(const pcr_grid& g, int C, bool yfast = false);
-// y-fastest storage when the detector's u axis is closer to y than to x
+// y-fastest storage for rays close to the x axis (the detector's u axis
+// close to y)
 bool prefer_yfast(const pcr_geom& G);
 
 // Per-projection ray geometry in index space, computed on the host in FP64.
@@ -75,7 +76,7 @@ struct MarchShape {
     int seg;             // ray segments (threads) per ray: 1, 2 or 4
     bool buffer_loads;   // FP32 march: raw buffer loads (else global loads)
 };
-MarchShape choose_march_shape(const RayGeom& rg);
+MarchShape choose_march_shape(const RayGeom& rg, bool yfast = false);
 
 // Moments returned by a ray march over channels (f, h_1..h_K):
 //   0 sum y, 1 sum y^2, 2 sum p, 3 sum y p, 4 sum p^2,

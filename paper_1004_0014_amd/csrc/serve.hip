@@ -45,6 +45,7 @@ struct Stream {
     double hist_w[3][8];
     double hist_t[3];
     int nhist = 0;
+    double mu_last = 0;   // step size the stream's last solve ended with
     bool active = false;
     bool removing = false;
     size_t bytes = 0;
@@ -74,6 +75,7 @@ struct Slot {
     SolveSM sm;
     double t_start = 0;
     double w0[8];
+    double mu0 = 0;
 };
 
 // Bytes of slot scratch a stream's solves need (fused image + partials +
@@ -143,7 +145,10 @@ bool pcr_server::start_slot(Slot& sl)
     }
     pcr_status e = sl.E.prepare(sl.req.y, sl.req.geom, PCR_GRAD_FUSED);
     if (e == PCR_OK) {
-        sl.sm.begin(st->model.K, st->opts, st->model.scale ? st->scale : nullptr, sl.w0);
+        pcr_solve_opts so = st->opts;
+        if (o.chain_step && st->mu_last > 0) so.mu0 = st->mu_last;
+        sl.mu0 = so.mu0;
+        sl.sm.begin(st->model.K, so, st->model.scale ? st->scale : nullptr, sl.w0);
         e = sl.E.enqueue_eval(sl.sm.eval_w());
     }
     if (e == PCR_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) e = PCR_EDEVICE;
@@ -170,6 +175,8 @@ void pcr_server::finish_slot(Slot& sl, pcr_status err)
         res.J = sl.sm.J;
         res.ab[0] = sl.sm.a;
         res.ab[1] = sl.sm.b;
+        res.mu0 = sl.mu0;
+        res.mu = sl.sm.mu;
         for (int k = 0; k < st->model.K; ++k) res.w[k] = sl.sm.w[k];
         if (st->opts.localize && (res.status == PCR_OK || res.status == PCR_ENOCONV)) {
             int32_t it = 0;
@@ -184,6 +191,7 @@ void pcr_server::finish_slot(Slot& sl, pcr_status err)
     std::lock_guard<std::mutex> lk(mu);
     if (err == PCR_OK && (res.status == PCR_OK || res.status == PCR_ENOCONV)) {
         for (int k = 0; k < st->model.K; ++k) st->w[k] = res.w[k];
+        st->mu_last = sl.sm.mu;
         if (st->nhist == 3) {
             for (int i = 0; i < 2; ++i) {
                 st->hist_t[i] = st->hist_t[i + 1];
@@ -502,6 +510,7 @@ pcr_status pcr_server_set_w(pcr_server* S, int32_t sid, const double* w)
     if (it->second->active) return fail(PCR_EBUSY, "stream %d has a solve in flight", sid);
     for (int k = 0; k < it->second->model.K; ++k) it->second->w[k] = w[k];
     it->second->nhist = 0;
+    it->second->mu_last = 0;
     return PCR_OK;
 }
 

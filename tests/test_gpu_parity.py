@@ -192,7 +192,7 @@ def test_cost_grad_across_layouts(tiny_case):
     c = tiny_case
     ctx = L.Context(c.grid, c.dmodel, c.df0)
     w = 0.6 * c.w_true
-    for ang in (30.0, 100.0, 200.0, 290.0, 44.0, 136.0):
+    for ang in (30.0, 100.0, 200.0, 290.0, 44.0, 136.0, 265.0, 82.0):
         G = c.geom.with_angle(math.radians(ang))
         x = oracle.compose(c.grid, c.mean, c.U, c.w_true)
         y_np = oracle.project(c.grid, G, oracle.warp(c.grid, c.f0, x))
@@ -386,4 +386,21 @@ def test_clipped_rays_are_exact(zero):
     evals = st["trials"] + 1          # the evaluation at w0, then one per trial
     full = support_box_samples(g, G)
     assert 0 <= st["samples"] < 0.7 * full * evals
+    ctx.close()
+
+
+def test_solve_with_given_first_step(tiny_case):
+    """opts.mu0 replaces step0 / |g_0| for the first trial, on both sides."""
+    L = _lib()
+    c = tiny_case
+    ctx = L.Context(c.grid, c.dmodel, c.df0)
+    y = torch.tensor(c.y, dtype=torch.float32, device=DEV)
+    w0 = 0.8 * c.w_true
+    for mu0 in (3e3, 4e4):
+        opts = L.default_opts(max_iter=20, step0=c.step0, mu0=mu0)
+        w, ab, st = ctx.reconstruct(y, c.geom, w0, opts)
+        wo, abo, sto, _ = oracle.solve(c.grid, c.geom, c.f0, c.mean, c.U, c.y, w0,
+                                       oracle.SolveOpts(max_iter=20, step0=c.step0, mu0=mu0))
+        assert rel_l2(w, wo) <= 1e-3
+        assert abs(st["mu"] - sto["mu"]) <= 1e-2 * sto["mu"]
     ctx.close()

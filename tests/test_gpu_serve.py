@@ -182,3 +182,29 @@ def test_predicted_warm_start(streams, order):
                          res[2]["t_submit_s"], order)
     assert np.allclose(res[2]["w0"], expect, rtol=1e-12, atol=1e-12)
     srv.close()
+
+
+def test_chained_step_size(streams):
+    """With chain_step each solve's first trial uses the step size the
+    stream's previous solve ended with; the result equals a blocking solve
+    given that step size (opts.mu0)."""
+    L = _L()
+    st = streams[2]
+    srv = L.Server(hbm_budget_bytes=4 << 30, max_slots=1, chain_step=True)
+    sid = srv.add_stream(st.grid, st.dm, st.df0, st.opts, np.zeros(st.K))
+    res = []
+    for j in range(3):
+        srv.submit(sid, st.ys[j], st.geoms[j])
+        srv.drain()
+        res += srv.poll(4)
+    assert res[0]["mu0"] == 0.0 and res[0]["mu"] > 0
+    for prev, cur in zip(res, res[1:]):
+        assert cur["mu0"] == prev["mu"]
+    ctx = L.Context(st.grid, st.dm, st.df0)
+    opts = L.default_opts(max_iter=25, step0=st.m.step0, localize=1,
+                          p_ref_mm=S.tumor_center(st.grid), mu0=res[2]["mu0"])
+    w, ab, sta = ctx.reconstruct(st.ys[2], st.geoms[2], res[2]["w0"], opts)
+    ctx.close()
+    assert w == res[2]["w"] and sta["trials"] == res[2]["trials"]
+    assert sta["mu"] == res[2]["mu"]
+    srv.close()

@@ -192,6 +192,19 @@ def test_line_search_on_exact_quadratic_is_block_coordinate_descent():
         assert st["iterations"] == N and st["trials"] == N
         np.testing.assert_allclose([w[0], a, b], ws[N - 1], rtol=1e-7, atol=1e-12)
     assert abs(ws[-1][0] - 0.37) < 1e-3
+    # a given first step size: mu0 = mu* makes every step the exact line
+    # minimiser, and the solver reports mu* as its next step size
+    for N in (1, 3):
+        opts = oracle.SolveOpts(max_iter=N, step0=1.0, eps_g=0.0, mu0=mu_star)
+        wo, (ao, bo), st, _ = oracle.solve(g, geom, f0, mean, U, y, [0.0], opts)
+        wm, am, bm = 0.0, *ab_of(0.0)
+        for n in range(N):
+            grad = 2.0 * float(np.sum(q * (p0 + wm * q - am * y - bm)))
+            wm = wm - mu_star * grad
+            am, bm = ab_of(wm)
+        assert st["trials"] == N
+        np.testing.assert_allclose([wo[0], ao, bo], [wm, am, bm], rtol=1e-7, atol=1e-12)
+        assert abs(st["mu"] - mu_star) <= 1e-6 * mu_star
 
 
 def test_localize_constant_dvf():
