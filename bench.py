@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
-    ap.add_argument("--variants", default="bf16,f16,adjoint,chain,predict,fluoro,fluoro-predict",
+    ap.add_argument("--variants", default="bf16,f16,f16-image,bf16-image,adjoint,chain,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
     ap.add_argument("--variant-steps", type=int, default=0,
                     help="steps of each variant (0: as many as the main run; the adjoint "
@@ -399,9 +399,10 @@ def main():
     for v in [s for s in args.variants.split(",") if s]:
         po = 0
         vsteps = min(Ks, args.variant_steps or (60 if v == "adjoint" else Ks))
-        if v in ("bf16", "f16"):
-            dm, f0v = storage_model(W, v, dev)
-            cv = _lib.Context(W.grid, dm, f0v)
+        if v in ("bf16", "f16", "bf16-image", "f16-image"):
+            dm, f0v = storage_model(W, v.split("-")[0], dev)
+            cv = _lib.Context(W.grid, dm, f0v,
+                              image_dtype=torch.float16 if v.endswith("image") else torch.float32)
             wv = run_sequence(cv, W, ys[:Wm], geoms[:Wm], idxs[:Wm], opts, [0.0] * K)
             rv = run_sequence(cv, W, ys[Wm:Wm + vsteps], geoms[Wm:Wm + vsteps],
                               idxs[Wm:Wm + vsteps], opts, wv["w"], profile=True)

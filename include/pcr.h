@@ -197,9 +197,9 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom,
 
 /* Backprojection P^T resid, the exact transpose of pcr_forward_project (the
  * P^T of the gradient formula in section 2.2; no factor 2).  resid_dev
- * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  Each
- * workgroup accumulates one brick of the output in LDS with LDS atomics
- * (order-dependent last bits; no global atomics). */
+ * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  A
+ * gather: each voxel sums the weights of the samples near it in a fixed
+ * order, so the result is deterministic (no atomics). */
 pcr_status pcr_backproject_residual(const pcr_grid* grid, const pcr_geom* geom,
                                     pcr_dtype compute, const void* resid_dev,
                                     void* vol_dev, void* stream);
@@ -214,6 +214,14 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
 void pcr_ctx_destroy(pcr_ctx* ctx);
 /* Bytes of device memory the context holds. */
 size_t pcr_ctx_device_bytes(const pcr_ctx* ctx);
+/* Element type of the context's fused image (the warped image and its K
+ * tangent images that each trial marches): PCR_F32 (default) or PCR_F16
+ * (FP32 compute only; each channel scaled by a power of two so that nothing
+ * overflows).  FP16 halves the bytes the march gathers per sample, but its
+ * rounding of the tangents adds gradient noise proportional to the residual,
+ * which slows the relative-gradient stop when the model cannot fit the data.
+ * Returns PCR_EINVAL for other types or FP64 compute. */
+pcr_status pcr_ctx_set_image_dtype(pcr_ctx* ctx, pcr_dtype dtype);
 
 /* Cost J(w, a, b) (eq. (2)) and its gradient dJ/dw (section 2.2, with the
  * factor 2) for the measured projection y_dev [nv][nu] (dtype = the
@@ -296,6 +304,7 @@ typedef struct pcr_server_opts {
                                  results at their submit times */
     int32_t chain_step;       /* nonzero: each solve's first trial uses the step size
                                  the stream's previous solve ended with (opts.mu0) */
+    int32_t image_f16;        /* nonzero: FP16 fused images (see pcr_ctx_set_image_dtype) */
 } pcr_server_opts;
 
 typedef struct pcr_result {

@@ -67,7 +67,7 @@ class SolveStats(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32),
-                ("predict_order", C.c_int32), ("chain_step", C.c_int32)]
+                ("predict_order", C.c_int32), ("chain_step", C.c_int32), ("image_f16", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -114,6 +114,7 @@ def lib():
             "pcr_ctx_create": (C.c_int32, [G, Md, C.c_int, _P, C.c_int, C.POINTER(_P)]),
             "pcr_ctx_destroy": (None, [_P]),
             "pcr_ctx_device_bytes": (C.c_size_t, [_P]),
+            "pcr_ctx_set_image_dtype": (C.c_int32, [_P, C.c_int]),
             "pcr_cost_grad": (C.c_int32, [_P, _P, Gm, _PD, C.c_double, C.c_double, C.c_int32,
                                           _PD, _PD, _P]),
             "pcr_reconstruct_from_projection": (C.c_int32, [_P, _P, Gm, C.POINTER(SolveOpts), _PD,
@@ -322,7 +323,8 @@ def default_opts(**kw) -> SolveOpts:
 class Context:
     """Solver context (pcr_ctx): binds grid, model and reference image."""
 
-    def __init__(self, grid, model: DeviceModel, f0: torch.Tensor, compute=torch.float32):
+    def __init__(self, grid, model: DeviceModel, f0: torch.Tensor, compute=torch.float32,
+                 image_dtype=torch.float32):
         self.grid = grid
         self.model = model
         self.f0 = f0.contiguous()
@@ -333,6 +335,8 @@ class Context:
         _check(lib().pcr_ctx_create(C.byref(self._g), C.byref(model.struct), _dtype(self.f0),
                                     _ptr(self.f0), _DT[compute], C.byref(h)))
         self._h = h
+        if image_dtype != torch.float32:
+            _check(lib().pcr_ctx_set_image_dtype(self._h, _DT[image_dtype]))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -390,9 +394,9 @@ class Server:
     into server-owned device memory at add_stream."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True,
-                 predict_order: int = 0, chain_step: bool = False):
+                 predict_order: int = 0, chain_step: bool = False, image_f16: bool = False):
         o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0, int(predict_order),
-                       1 if chain_step else 0)
+                       1 if chain_step else 0, 1 if image_f16 else 0)
         h = C.c_void_p()
         _check(lib().pcr_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -272,10 +272,10 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     const int Cc = channels_for(model->K + 1);
     const size_t esz = dtype_size(compute);
     sc->Lc = make_pad(*grid, Cc, yfast);
-    // 16-bit storage of the model: the fused image in FP16 too (half the
-    // bytes per tap for the march), FP32 arithmetic and FP64 moments
-    if (compute == PCR_F32 && (model->storage == PCR_BF16 || model->storage == PCR_F16) && sup &&
-        sup->valid) {
+    // FP16 fused image on request: half the bytes per tap for the march,
+    // FP32 arithmetic and FP64 moments; the channel scales need the bounds
+    // the support pass records
+    if (image_f16 && compute == PCR_F32 && sup && sup->valid) {
         sc->Lc.half = true;
         half_scales(*sup, *grid, model->K, sc->Lc.hs);
     }
@@ -745,6 +745,7 @@ struct pcr_ctx {
     const void* f0;
     Scratch sc;
     Support sup;   // computed on the first evaluation
+    bool image_f16 = false;
     ~pcr_ctx() { sc.release(); }
 };
 
@@ -792,6 +793,16 @@ void pcr_ctx_destroy(pcr_ctx* ctx)
 
 size_t pcr_ctx_device_bytes(const pcr_ctx* c) { return c ? c->sc.device_bytes() : 0; }
 
+pcr_status pcr_ctx_set_image_dtype(pcr_ctx* ctx, pcr_dtype dtype)
+{
+    if (!ctx) return fail(PCR_EINVAL, "ctx is NULL");
+    if (dtype != PCR_F32 && dtype != PCR_F16) return fail(PCR_EINVAL, "image dtype must be F32 or F16");
+    if (dtype == PCR_F16 && ctx->compute != PCR_F32)
+        return fail(PCR_EINVAL, "an FP16 image needs FP32 compute");
+    ctx->image_f16 = dtype == PCR_F16;
+    return PCR_OK;
+}
+
 pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
                          const double* w_host, double a, double b, int32_t grad_mode,
                          double* cost_host, double* grad_host, void* stream)
@@ -811,6 +822,7 @@ pcr_status pcr_cost_grad(pcr_ctx* ctx, const void* y_dev, const pcr_geom* geom,
     Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
                 (hipStream_t)stream};
     E.sup = &ctx->sup;
+    E.image_f16 = ctx->image_f16;
     PCR_TRY(E.prepare(y_dev, *geom, grad_mode));
     Moments mo;
     PCR_TRY(E.eval_sync(w_host, mo));
@@ -843,6 +855,7 @@ pcr_status pcr_reconstruct_from_projection(pcr_ctx* ctx, const void* y_dev, cons
     Evaluator E{&ctx->grid, &ctx->model, ctx->f0_dtype, ctx->compute, ctx->f0, &ctx->sc,
                 (hipStream_t)stream};
     E.sup = &ctx->sup;
+    E.image_f16 = ctx->image_f16;
     PCR_TRY(E.prepare(y_dev, *geom, opts->grad_mode));
     SolveSM sm;
     sm.begin(K, *opts, ctx->model.scale ? ctx->scale : nullptr, w_inout);

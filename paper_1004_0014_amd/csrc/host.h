@@ -175,6 +175,7 @@ struct Evaluator {
     Scratch* sc;
     hipStream_t s;
     const Support* sup = nullptr;   // null: rays span the whole support box
+    bool image_f16 = false;         // FP16 fused image (FP32 compute, support known)
     // per projection
     const void* y = nullptr;
     RayGeom rg{}, rgc{};

@@ -823,18 +823,22 @@ __global__ void __launch_bounds__(256) k_absmax_rows(const S* __restrict__ a, si
 // P^T r as a gather: every output voxel sums, over the rays whose samples can
 // touch it, r * dt * (its trilinear weight) at each sample -- the weight the
 // forward march gives that voxel as a corner of the sample's cell, i.e.
-// prod_a max(0, 1 - |q_a - v_a|).  No atomics; each voxel accumulates in a
-// fixed order, so the result is deterministic.
+// prod_a max(0, 1 - |q_a - v_a|).  No global atomics, and every voxel's sum
+// is formed in a fixed order, so the result is deterministic.
 //
-// A workgroup owns a brick of 256 voxels (elongated along the rays'
-// dominant in-plane axis, which keeps its detector footprint small).  It
-// walks the footprint in 16 x 16 pixel tiles: per tile every thread stages
-// one ray in LDS -- the sample nearest the brick centre (relative to the
-// brick origin), the step per sample, its reciprocal, r dt and the valid
-// sample range [0, floor(L / dt)] -- then each voxel visits the rays of the
-// tile inside its own footprint (the detector box of its projected
-// (v - 1, v + 1)^3 neighbourhood) and, per ray, the samples whose slab test
-// puts them inside that neighbourhood.
+// A workgroup owns a brick of 16 x 4 x 4 voxels whose long side runs along
+// the rays' dominant in-plane axis A: 16 columns of 16 voxels along A.  It
+// walks the brick's detector footprint in 16 x 16 pixel tiles; per tile every
+// thread stages one ray in LDS (the sample nearest the brick centre relative
+// to the brick origin, the step per sample, slab bounds, r dt and the valid
+// sample range [0, floor(L / dt)]).  Then the 16 threads of a column split
+// the rays of the column's own footprint between them; for each ray a slab
+// test gives the samples that pass within one voxel of the column's line,
+// and each such sample adds its weight to the two voxels of the column that
+// straddle it along A (a per-thread run of 16 accumulators in LDS).  Per ray
+// the set-up is paid once per column instead of once per voxel, and each
+// sample is visited once.  A fixed-order sum over the 16 threads of each
+// column gives the voxel values.
 struct BPFoot {
     // for an index-space point X: a = a0 + an.X (depth along the central
     // ray, mm), b = b0 + bn.X and c = c0 + cn.X (offsets along e_u, e_v);
@@ -881,50 +885,63 @@ __device__ __forceinline__ void footprint(const BPFoot& F, const float lo[3], co
 struct BPArgs {
     RayGeom g;            // unswapped (x-fastest) geometry
     BPFoot F;
-    int bx, by, bz;       // brick (bx * by * bz == 256)
+    int ax;               // column axis A: 0 (x) or 1 (y)
+    int bx, by, bz;       // brick: 16 along A, 4 along the other two axes
     int nbx, nby;         // bricks per axis
     int nx, ny, nz;
     double a, b, scale;   // r = scale (p - a y - b) when no residual is given
 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* __restrict__ resid,
-                                                            const R* __restrict__ p,
-                                                            const R* __restrict__ y,
-                                                            R* __restrict__ out)
+__global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* __restrict__ resid,
+                                                             const R* __restrict__ p,
+                                                             const R* __restrict__ y,
+                                                             R* __restrict__ out)
 {
     __shared__ R s_q[3][256];      // nearest sample to the brick centre, minus the brick origin
     __shared__ R s_d[3][256];      // index-space step per sample
     __shared__ float s_inv[3][256];
-    // slab bounds in samples for the voxel at the brick origin: voxel l
-    // (brick-local) sees samples m in (lo_a + l_a inv_a, hi_a + l_a inv_a)
-    __shared__ float s_lo[3][256], s_hi[3][256];
+    // slab bounds in samples: |q_a + m d_a - l| < 1 for m in
+    // (lo_a + l inv_a, hi_a + l inv_a); along A the whole column (-1, 16)
+    __shared__ float s_lo[3][256], s_hi[3][256], s_la[256], s_ha[256];
     __shared__ R s_rw[256];        // r dt
     __shared__ int s_m[2][256];    // valid sample offsets [m0, m1] from that sample
+    // thread (lane, column): 16 voxels along A at [2, 18) of a run of 21
+    // (two pad slots each side take the clipped weights of samples just
+    // outside the column, so the accumulation needs no branch)
+    __shared__ R s_acc[256 * 21];
     __shared__ int s_box[4];
     const RayGeom& g = A.g;
     const int t = threadIdx.x;
     const int bid = blockIdx.x;
     const int b0[3] = {(bid % A.nbx) * A.bx, ((bid / A.nbx) % A.nby) * A.by, (bid / (A.nbx * A.nby)) * A.bz};
-    const int l[3] = {t % A.bx, (t / A.bx) % A.by, t / (A.bx * A.by)};
-    const int v[3] = {b0[0] + l[0], b0[1] + l[1], b0[2] + l[2]};
-    const bool inside = v[0] < A.nx && v[1] < A.ny && v[2] < A.nz;
+    const int AX = A.ax, BX = 1 - A.ax;           // column axis and the other in-plane axis
+    const int col = t & 15, lane = t >> 4;        // column (lb, lz) and ray lane
+    const int lb = col & 3, lz = col >> 2;
+    for (int e = t; e < 256 * 21; e += 256) s_acc[e] = (R)0;
+    R* acc = s_acc + (lane * 16 + col) * 21 + 2;
     if (t == 0) {
         const float lo[3] = {(float)(b0[0] - 1), (float)(b0[1] - 1), (float)(b0[2] - 1)};
         const float hi[3] = {(float)(b0[0] + A.bx), (float)(b0[1] + A.by), (float)(b0[2] + A.bz)};
         footprint(A.F, lo, hi, 1.0f, s_box[0], s_box[1], s_box[2], s_box[3]);
     }
-    int ru0 = 0, ru1 = -1, rv0 = 0, rv1 = -1;
-    if (inside) {
-        const float lo[3] = {(float)(v[0] - 1), (float)(v[1] - 1), (float)(v[2] - 1)};
-        const float hi[3] = {(float)(v[0] + 1), (float)(v[1] + 1), (float)(v[2] + 1)};
+    // the column's footprint: its line (-1, 16) along A, one voxel around it
+    int ru0, ru1, rv0, rv1;
+    {
+        float lo[3], hi[3];
+        lo[AX] = (float)(b0[AX] - 1);
+        hi[AX] = (float)(b0[AX] + 16);
+        lo[BX] = (float)(b0[BX] + lb - 1);
+        hi[BX] = (float)(b0[BX] + lb + 1);
+        lo[2] = (float)(b0[2] + lz - 1);
+        hi[2] = (float)(b0[2] + lz + 1);
         footprint(A.F, lo, hi, 0.02f, ru0, ru1, rv0, rv1);
     }
     __syncthreads();
     const int bu0 = s_box[0], bu1 = s_box[1], bv0 = s_box[2], bv1 = s_box[3];
     const double cb[3] = {b0[0] + 0.5 * (A.bx - 1), b0[1] + 0.5 * (A.by - 1), b0[2] + 0.5 * (A.bz - 1)};
-    const R lr[3] = {(R)l[0], (R)l[1], (R)l[2]};
-    R acc = (R)0;
+    const float flb = (float)lb, flz = (float)lz;
+    const R rlb = (R)lb, rlz = (R)lz;
     for (int tv0 = bv0; tv0 <= bv1; tv0 += 16) {
         for (int tu0 = bu0; tu0 <= bu1; tu0 += 16) {
             {   // stage one ray per thread (FP64 set-up, once per ray and brick)
@@ -975,47 +992,69 @@ __global__ void __launch_bounds__(256) k_backproject_gather(BPArgs A, const R* _
                     s_inv[ax][t] = inv;
                     s_lo[ax][t] = fminf(e1, e2);
                     s_hi[ax][t] = fmaxf(e1, e2);
+                    if (ax == AX) {
+                        const float e3 = (16.0f - (float)qr[ax]) * inv;
+                        s_la[t] = fminf(e1, e3);
+                        s_ha[t] = fmaxf(e1, e3);
+                    }
                 }
                 s_rw[t] = rw;
                 s_m[0][t] = m0;
                 s_m[1][t] = m1;
             }
             __syncthreads();
+            // rays of this tile inside the column's footprint, split over the
+            // column's 16 lanes
             const int ua = max(ru0, tu0), ub = min(ru1, tu0 + 15);
             const int va = max(rv0, tv0), vb = min(rv1, tv0 + 15);
-            for (int iv = va; iv <= vb; ++iv) {
-                for (int iu = ua; iu <= ub; ++iu) {
-                    const int k = ((iv - tv0) << 4) + (iu - tu0);
-                    // samples m with |q_m - l| < 1 on every axis (slab test;
-                    // the 1e-3 sample slack covers the FP32 rounding of the
-                    // bounds, and the weights clip any sample it admits)
-                    const float lx = (float)l[0], ly = (float)l[1], lz = (float)l[2];
-                    const float ix = s_inv[0][k], iy = s_inv[1][k], iz = s_inv[2][k];
-                    float lo = fmaxf(fmaxf(fmaf(lx, ix, s_lo[0][k]), fmaf(ly, iy, s_lo[1][k])),
-                                     fmaf(lz, iz, s_lo[2][k]));
-                    float hi = fminf(fminf(fmaf(lx, ix, s_hi[0][k]), fmaf(ly, iy, s_hi[1][k])),
-                                     fmaf(lz, iz, s_hi[2][k]));
-                    lo = fminf(fmaxf(lo, -1.0e6f), 1.0e6f);   // |m| stays far inside int range
-                    hi = fminf(fmaxf(hi, -1.0e6f), 1.0e6f);
-                    const int m0 = max(s_m[0][k], (int)ceilf(lo - 1.0e-3f));
-                    const int m1 = min(s_m[1][k], (int)floorf(hi + 1.0e-3f));
-                    if (m0 > m1) continue;
-                    const R rx = s_q[0][k] - lr[0], ry = s_q[1][k] - lr[1], rz = s_q[2][k] - lr[2];
-                    const R dx = s_d[0][k], dy = s_d[1][k], dz = s_d[2][k];
-                    const R rw = s_rw[k];
-                    for (int m = m0; m <= m1; ++m) {
-                        const R fm = (R)m;
-                        const R wx = fmax((R)0, (R)1 - fabs(fma(fm, dx, rx)));
-                        const R wy = fmax((R)0, (R)1 - fabs(fma(fm, dy, ry)));
-                        const R wz = fmax((R)0, (R)1 - fabs(fma(fm, dz, rz)));
-                        acc = fma(wx * wy * wz, rw, acc);
-                    }
+            const int wu = ub - ua + 1, nr = (ub >= ua && vb >= va) ? wu * (vb - va + 1) : 0;
+            for (int i = lane; i < nr; i += 16) {
+                const int iu = ua + i % wu, iv = va + i / wu;
+                const int k = ((iv - tv0) << 4) + (iu - tu0);
+                // samples within one voxel of the column line (slab test; the
+                // 1e-3 sample slack covers the FP32 rounding of the bounds and
+                // the weights clip any sample it admits)
+                const float ib = s_inv[BX][k], iz = s_inv[2][k];
+                float lo = fmaxf(fmaxf(s_la[k], fmaf(flb, ib, s_lo[BX][k])), fmaf(flz, iz, s_lo[2][k]));
+                float hi = fminf(fminf(s_ha[k], fmaf(flb, ib, s_hi[BX][k])), fmaf(flz, iz, s_hi[2][k]));
+                lo = fminf(fmaxf(lo, -1.0e6f), 1.0e6f);   // |m| stays far inside int range
+                hi = fminf(fmaxf(hi, -1.0e6f), 1.0e6f);
+                const int m0 = max(s_m[0][k], (int)ceilf(lo - 1.0e-3f));
+                const int m1 = min(s_m[1][k], (int)floorf(hi + 1.0e-3f));
+                if (m0 > m1) continue;
+                const R qa = s_q[AX][k], qb = s_q[BX][k] - rlb, qz = s_q[2][k] - rlz;
+                const R da = s_d[AX][k], db = s_d[BX][k], dz = s_d[2][k];
+                const R rw = s_rw[k];
+                for (int m = m0; m <= m1; ++m) {
+                    const R fm = (R)m;
+                    const R wbz = fmax((R)0, (R)1 - fabs(fma(fm, db, qb))) *
+                                  fmax((R)0, (R)1 - fabs(fma(fm, dz, qz))) * rw;
+                    const R xa = fma(fm, da, qa);
+                    const R fl = floor(xa);
+                    // the slab range keeps xa within (-1.01, 16.01); the clamp
+                    // only guards the LDS run
+                    const int j = min(max((int)fl, -2), 16);
+                    const R fa = xa - fl;
+                    // the thread's own LDS run: a plain read-modify-write
+                    acc[j] += ((R)1 - fa) * wbz;
+                    acc[j + 1] += fa * wbz;
                 }
             }
             __syncthreads();
         }
     }
-    if (inside) out[(size_t)v[0] + (size_t)A.nx * ((size_t)v[1] + (size_t)A.ny * v[2])] = acc;
+    // voxel (column c, position j along A): the sum over the column's 16 lanes
+    {
+        const int c = t >> 4, j = t & 15;
+        R v = (R)0;
+        for (int l = 0; l < 16; ++l) v += s_acc[(l * 16 + c) * 21 + 2 + j];
+        int vx[3];
+        vx[AX] = b0[AX] + j;
+        vx[BX] = b0[BX] + (c & 3);
+        vx[2] = b0[2] + (c >> 2);
+        if (vx[0] < A.nx && vx[1] < A.ny && vx[2] < A.nz)
+            out[(size_t)vx[0] + (size_t)A.nx * ((size_t)vx[1] + (size_t)A.ny * vx[2])] = v;
+    }
 }
 
 // ---------------------------------------------------------- contraction --
@@ -1596,7 +1635,7 @@ hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeo
     A.F.nv = rg.nv;
     // bricks elongated along the rays' dominant in-plane axis
     const double rx = std::fabs(rg.qc[0] - rg.qs[0]) * rg.sp[0], ry = std::fabs(rg.qc[1] - rg.qs[1]) * rg.sp[1];
-    if (ry >= rx) { A.bx = 4; A.by = 16; } else { A.bx = 16; A.by = 4; }
+    if (ry >= rx) { A.ax = 1; A.bx = 4; A.by = 16; } else { A.ax = 0; A.bx = 16; A.by = 4; }
     A.bz = 4;
     A.nx = g.n[0];
     A.ny = g.n[1];
@@ -1610,7 +1649,7 @@ hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeo
     const long blocks = (long)A.nbx * A.nby * nbz;
     if (blocks <= 0 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     PCR_DISPATCH_R(compute, R,
-        k_backproject_gather<R><<<(unsigned)blocks, 256, 0, s>>>(A, (const R*)resid, (const R*)p,
+        k_backproject_columns<R><<<(unsigned)blocks, 256, 0, s>>>(A, (const R*)resid, (const R*)p,
                                                                 (const R*)y, (R*)out));
     return hipGetLastError();
 }

@@ -130,6 +130,7 @@ bool pcr_server::start_slot(Slot& sl)
     Stream* st = sl.st;
     sl.E = Evaluator{&st->grid, &st->model, st->f0_dtype, PCR_F32, st->f0.p, &sl.sc, sl.s};
     sl.E.sup = &st->sup;
+    sl.E.image_f16 = o.image_f16 != 0;
     sl.t_start = now_s();
     for (int k = 0; k < 8; ++k) sl.w0[k] = k < st->model.K ? st->w[k] : 0.0;
     if (o.predict_order > 0 && st->nhist >= 2) {

@@ -29,6 +29,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--image", default="f32", choices=["f32", "f16"],
+                    help="element type of the fused image")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     g = S.grid_for(args.config)
@@ -43,7 +45,7 @@ def main():
     y = _lib.forward_project(g, G, _lib.warp_volume(g, f0, _lib.dvf_compose(g, dm32, w)))
     dm = dm32 if dt == torch.float32 else _lib.DeviceModel(dm32.mean.to(dt), dm32.U.to(dt))
     f0s = f0.to(dt)
-    ctx = _lib.Context(g, dm, f0s)
+    ctx = _lib.Context(g, dm, f0s, image_dtype=torch.float16 if args.image == "f16" else torch.float32)
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -56,8 +58,8 @@ def main():
             _lib.forward_project(g, G, f0)
         dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written
     torch.cuda.synchronize()
-    print("kprof done: %s x%d at %s, %s storage" % (args.what, args.reps, args.config, args.storage),
-          file=sys.stderr)
+    print("kprof done: %s x%d at %s, %s storage, %s image" % (args.what, args.reps, args.config,
+                                                             args.storage, args.image), file=sys.stderr)
 
 
 if __name__ == "__main__":

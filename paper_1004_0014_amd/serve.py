@@ -175,9 +175,9 @@ def build_streams(n_streams, seconds, seed, dev):
 
 
 # ----------------------------------------------------------------- run -----
-def run(streams, seconds, max_slots, budget_gb, drop_stale=True):
+def run(streams, seconds, max_slots, budget_gb, drop_stale=True, image_f16=False):
     srv = _lib.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=max_slots,
-                      drop_stale=drop_stale)
+                      drop_stale=drop_stale, image_f16=image_f16)
     sids, rejected = [], 0
     for st in streams:
         try:
@@ -246,12 +246,13 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--image-f16", action="store_true", help="FP16 fused images")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     counts = [int(s) for s in args.streams.split(",")]
     streams = build_streams(max(counts), args.seconds, args.seed, dev)
     for n in counts:
-        res = run(streams[:n], args.seconds, args.slots, args.budget_gb)
+        res = run(streams[:n], args.seconds, args.slots, args.budget_gb, image_f16=args.image_f16)
         print(json.dumps({"serving": res}), flush=True)
 
 
