@@ -33,8 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "p50/p99 per-projection solve latency; solves/s served; ray-samples/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU issue rate without packed-FP32 instructions (which this build
-# disables): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+# FP32 VALU issue rate without packed-FP32 instructions (which the library's
+# compile flags disable): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
 # (78.6 TFLOP/s counting an FMA as two flops).
 VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # vector L1 delivery: 64 B per clock per CU
