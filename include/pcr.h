@@ -319,6 +319,8 @@ typedef struct pcr_result {
     double t_submit_s, t_start_s, t_done_s;   /* steady-clock seconds */
     double mu0, mu;           /* step size of the first trial, and the one the solve
                                  ended with (see pcr_solve_opts.mu0) */
+    double samples;           /* ray samples marched over all projections of the
+                                 solve (the work it took; see pcr_solve_stats) */
 } pcr_result;
 
 /* Creates the server and its worker thread on the current device. */

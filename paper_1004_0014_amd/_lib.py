@@ -76,7 +76,7 @@ class Result(C.Structure):
                 ("fp_status", C.c_int32), ("w0", C.c_double * 8), ("w", C.c_double * 8),
                 ("ab", C.c_double * 2), ("J", C.c_double), ("tumor_mm", C.c_double * 3),
                 ("t_submit_s", C.c_double), ("t_start_s", C.c_double), ("t_done_s", C.c_double),
-                ("mu0", C.c_double), ("mu", C.c_double)]
+                ("mu0", C.c_double), ("mu", C.c_double), ("samples", C.c_double)]
 
     def as_dict(self):
         K = self.K
@@ -85,7 +85,7 @@ class Result(C.Structure):
                 "w0": list(self.w0[:K]), "w": list(self.w[:K]), "ab": list(self.ab), "J": self.J,
                 "tumor_mm": list(self.tumor_mm), "t_submit_s": self.t_submit_s,
                 "t_start_s": self.t_start_s, "t_done_s": self.t_done_s, "mu0": self.mu0,
-                "mu": self.mu}
+                "mu": self.mu, "samples": self.samples}
 
 
 _lib = None

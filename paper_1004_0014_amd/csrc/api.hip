@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "host.h"
+#include "scheduler.h"
 
 using namespace pcr;
 
@@ -287,7 +288,7 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     if (mode == PCR_GRAD_FUSED) {
         const size_t need = sc->Lc.cells() * sc->Lc.cell_bytes(esz);
         bool fresh = sc->volc.p == nullptr || sc->volc.bytes < need;
-        PCR_TRY(sc->volc.ensure(need, dev, s));
+        PCR_TRY(sc->volc.ensure(std::max(need, sc->volc_floor), dev, s));
         if (fresh || !sc->volc_zeroed || !sc->volc_layout.same_storage(sc->Lc)) {
             // border cells of one layout (grid, channel count, element
             // type, axis order) are interior cells of another
@@ -693,14 +694,7 @@ pcr_status pcr_predict_w(const double* w_hist, const double* t_hist, int32_t n, 
     const int first = n - 1 - d;
     for (int i = first + 1; i < n; ++i)
         if (!(t_hist[i] > t_hist[i - 1])) return fail(PCR_EINVAL, "t_hist must increase");
-    // Lagrange form of the interpolating polynomial through points first..n-1
-    for (int k = 0; k < K; ++k) w_out[k] = 0.0;
-    for (int i = first; i < n; ++i) {
-        double L = 1.0;
-        for (int j = first; j < n; ++j)
-            if (j != i) L *= (t_next - t_hist[j]) / (t_hist[i] - t_hist[j]);
-        for (int k = 0; k < K; ++k) w_out[k] += L * w_hist[i * K + k];
-    }
+    sched::extrapolate_w(w_hist, t_hist, n, K, t_next, order, w_out);
     return PCR_OK;
 }
 

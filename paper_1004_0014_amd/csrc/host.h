@@ -132,6 +132,8 @@ struct Scratch {
     PadLayout Lc{}, L1{};
     PadLayout volc_layout{};   // layout whose zero borders volc holds
     bool volc_zeroed = false;
+    size_t volc_floor = 0;     // allocate volc at least this large (a serving slot
+                               // sized once for every admitted stream)
     DevBuf volc, vol1, acc1, p, partials, moments;
     HostBuf host;
     void release();

@@ -235,6 +235,10 @@ def run(streams, seconds, max_slots, budget_gb, drop_stale=True, image_f16=False
         "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
         "queue_wait_p50_ms": float(np.percentile(wait, 50)) if len(wait) else None,
         "mean_iterations": float(np.mean([r["iterations"] for r in served])) if served else None,
+        # work-normalised rate: ray samples marched by the served solves per
+        # second (mixes of different sizes are comparable on it)
+        "served_gsamples_per_s": sum(r["samples"] for r in served) / span * 1e-9,
+        "mean_gsamples_per_solve": float(np.mean([r["samples"] for r in served])) * 1e-9 if served else None,
         "w_rel_err_median": float(np.median(werr)) if werr else None,
     }
 

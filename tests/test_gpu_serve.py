@@ -90,6 +90,7 @@ def test_mix_equals_alone_bitwise(streams):
         assert w == r["w"], (r["req_id"], w, r["w"])          # bitwise
         assert list(ab) == r["ab"]
         assert sta["iterations"] == r["iterations"] and sta["trials"] == r["trials"]
+        assert sta["samples"] == r["samples"] > 0
         assert np.allclose(sta["tumor_mm"], r["tumor_mm"], rtol=0, atol=0)
     # warm starts chain: each stream's frame j started from its frame j-1 result
     by_stream = {}
