@@ -388,6 +388,18 @@ void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, 
     }
 }
 
+void warp_box(const RayGeom& g, const pcr_grid& grid, int box[6])
+{
+    for (int a = 0; a < 3; ++a) {
+        // a ray's samples lie within one step (dt / s_a voxels) of the clip
+        // box; each reads the cells floor(q) and floor(q) + 1; one more cell
+        // on each side covers the FP32 rounding of the sample positions
+        const double e = g.dt / g.sp[a];
+        box[a] = std::max(0, (int)std::floor(g.clo[a] - e) - 1);
+        box[3 + a] = std::min(grid.n[a], (int)std::floor(g.chi[a] + e) + 3);
+    }
+}
+
 pcr_status Evaluator::enqueue_eval(const double* w)
 {
     double w_eff[8];
@@ -396,15 +408,19 @@ pcr_status Evaluator::enqueue_eval(const double* w)
     const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
     double* mom = (double*)sc->moments.p;
     RayGeom gc = rgc, g1 = rg;
+    int vbox[6];
+    const int* box = nullptr;
     if (sup && sup->valid) {
         clip_box(*sup, *grid, K, w_eff, sc->Lc.yfast, gc.clo, gc.chi);
         clip_box(*sup, *grid, K, w_eff, false, g1.clo, g1.chi);
+        warp_box(g1, *grid, vbox);
+        box = vbox;
     }
     if (mode == PCR_GRAD_FUSED) {
         {
             PROF(WARP, s);
             HIP_TRY(launch_warp_fused(compute, model->storage, f0_dtype, *grid, sc->Lc, K, true, f0,
-                                      model->mean, model->U, w_eff, sc->volc.p, s));
+                                      model->mean, model->U, w_eff, box, sc->volc.p, s));
         }
         {
             PROF(MARCH, s);
@@ -415,7 +431,7 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         {
             PROF(WARP, s);
             HIP_TRY(launch_warp_fused(compute, model->storage, f0_dtype, *grid, sc->L1, K, false, f0,
-                                      model->mean, model->U, w_eff, sc->vol1.p, s));
+                                      model->mean, model->U, w_eff, box, sc->vol1.p, s));
         }
         {
             PROF(MARCH, s);

@@ -168,6 +168,10 @@ pcr_status compute_support(const pcr_grid& g, const pcr_model& m, pcr_dtype f0_d
 // Ray clip box (index space; x and y swapped for the y-fastest layout).
 void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
               double clo[3], double chi[3]);
+// Voxels {lo x, lo y, lo z, hi x, hi y, hi z} (hi exclusive) whose cells the
+// samples of rays clipped to g's box can read (grid axis order): the warp
+// computes only these, since no other cell is sampled.
+void warp_box(const RayGeom& g, const pcr_grid& grid, int box[6]);
 
 struct Evaluator {
     const pcr_grid* grid;

@@ -283,17 +283,23 @@ __device__ __forceinline__ CellOf<R, C, H> store_cell(const Chan<R, C>& o, const
     }
 }
 
+// Voxels [lo, hi) per axis that a launch computes.
+struct VoxBox {
+    int lo[3], hi[3];
+};
+
 // x-fastest padded layout: block 64 (x) x 4 (y), coalesced in x both ways.
 template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
                                                     const S* __restrict__ mean,
                                                     const S* __restrict__ U, int K,
                                                     Chan<double, 8> w, VoxGrid g, int px, int py,
-                                                    Chan<float, 8> hs,
+                                                    Chan<float, 8> hs, VoxBox b,
                                                     CellOf<R, C, H>* __restrict__ out)
 {
-    int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny) return;
+    const int i = b.lo[0] + blockIdx.x * 64 + threadIdx.x, j = b.lo[1] + blockIdx.y * 4 + threadIdx.y;
+    const int k = b.lo[2] + blockIdx.z;
+    if (i >= b.hi[0] || j >= b.hi[1]) return;
     Chan<R, C> o = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
     out[(size_t)(i + 1) + (size_t)px * ((size_t)(j + 1) + (size_t)py * (k + 1))] =
         store_cell<R, C, H>(o, hs);
@@ -306,16 +312,16 @@ __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        const S* __restrict__ mean,
                                                        const S* __restrict__ U, int K,
                                                        Chan<double, 8> w, VoxGrid g, int px,
-                                                       int py, Chan<float, 8> hs,
+                                                       int py, Chan<float, 8> hs, VoxBox b,
                                                        CellOf<R, C, H>* __restrict__ out)
 {
     __shared__ CellOf<R, C, H> tile[32][33];
-    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;
+    const int i0 = b.lo[0] + blockIdx.x * 32, j0 = b.lo[1] + blockIdx.y * 32, k = b.lo[2] + blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = i0 + tx, j = j0 + ty + 8 * r;
-        if (i < g.nx && j < g.ny)
+        if (i < b.hi[0] && j < b.hi[1])
             tile[ty + 8 * r][tx] = store_cell<R, C, H>(warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k), hs);
     }
     __syncthreads();
@@ -323,7 +329,7 @@ __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
     for (int r = 0; r < 4; ++r) {
         const int jl = tx, il = ty + 8 * r;
         const int i = i0 + il, j = j0 + jl;
-        if (i < g.nx && j < g.ny)
+        if (i < b.hi[0] && j < b.hi[1])
             out[(size_t)(j + 1) + (size_t)px * ((size_t)(i + 1) + (size_t)py * (k + 1))] = tile[jl][il];
     }
 }
@@ -1412,19 +1418,26 @@ hipError_t launch_warp_plain(pcr_dtype compute, pcr_dtype f0_dtype, const pcr_gr
 template <typename R, typename S, typename F>
 static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, bool tangent,
                                const void* f0, const void* mean, const void* U,
-                               const double* w_eff, void* padded, hipStream_t s)
+                               const double* w_eff, const int* box, void* padded, hipStream_t s)
 {
-    dim3 grid = vox_grid(g), blk(64, 4);
+    VoxBox b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = box ? std::max(0, box[a]) : 0;
+        b.hi[a] = box ? std::min(g.n[a], box[3 + a]) : g.n[a];
+        if (b.hi[a] <= b.lo[a]) return hipSuccess;   // nothing to compute
+    }
+    const int ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+    dim3 grid((ex + 63) / 64, (ey + 3) / 4, ez), blk(64, 4);
     auto w = wvec(w_eff, K);
-    dim3 grid_yf((g.n[0] + 31) / 32, (g.n[1] + 31) / 32, g.n[2]);
+    dim3 grid_yf((ex + 31) / 32, (ey + 31) / 32, ez);
     Chan<float, 8> hs;
     for (int c = 0; c < 8; ++c) hs.v[c] = L.hs[c];
 #define PCR_WF2(C, T, H)                                                                          \
     (L.yfast ? k_warp_fused_yf<R, S, F, C, T, H><<<grid_yf, 256, 0, s>>>(                         \
-                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs,       \
+                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs, b,    \
                    (CellOf<R, C, H>*)padded)                                                      \
              : k_warp_fused<R, S, F, C, T, H><<<grid, blk, 0, s>>>(                               \
-                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs,       \
+                   (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs, b,    \
                    (CellOf<R, C, H>*)padded))
 #define PCR_WF(C, T) (L.half ? PCR_WF2(C, T, true) : PCR_WF2(C, T, false))
     if (L.half && !std::is_same<R, float>::value) return hipErrorInvalidValue;
@@ -1452,10 +1465,10 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
 hipError_t launch_warp_fused(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
                              const pcr_grid& g, const PadLayout& L, int K, bool tangent,
                              const void* f0, const void* mean, const void* U,
-                             const double* w_eff, void* padded, hipStream_t s)
+                             const double* w_eff, const int* box, void* padded, hipStream_t s)
 {
     PCR_DISPATCH_R(compute, R, PCR_DISPATCH_S(storage, S, PCR_DISPATCH_S(f0_dtype, F,
-        return warp_fused_c<R, S, F>(g, L, K, tangent, f0, mean, U, w_eff, padded, s))));
+        return warp_fused_c<R, S, F>(g, L, K, tangent, f0, mean, U, w_eff, box, padded, s))));
     return hipSuccess;
 }
 

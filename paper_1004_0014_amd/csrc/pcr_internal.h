@@ -97,11 +97,14 @@ hipError_t launch_compose(pcr_dtype compute, pcr_dtype storage, const pcr_grid& 
 hipError_t launch_warp_plain(pcr_dtype compute, pcr_dtype f0_dtype, const pcr_grid& g,
                              const void* f0, const void* dvf, void* f, hipStream_t s);
 // Fused compose + warp (+ tangents): writes channel 0 = f and, when
-// tangent, channels 1..K = h_k = (df/dx) . u_k into the padded layout.
+// tangent, channels 1..K = h_k = (df/dx) . u_k into the padded layout, for
+// the voxels of box {lo x, lo y, lo z, hi x, hi y, hi z} (hi exclusive,
+// clamped to the grid; null = every voxel).  Cells outside it keep what they
+// held.
 hipError_t launch_warp_fused(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
                              const pcr_grid& g, const PadLayout& L, int K, bool tangent,
                              const void* f0, const void* mean, const void* U,
-                             const double* w_eff, void* padded, hipStream_t s);
+                             const double* w_eff, const int* box, void* padded, hipStream_t s);
 hipError_t launch_pad(pcr_dtype compute, const PadLayout& L, const void* vol, void* padded,
                       hipStream_t s);
 hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padded, void* vol,

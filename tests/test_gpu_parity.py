@@ -389,6 +389,36 @@ def test_clipped_rays_are_exact(zero):
     ctx.close()
 
 
+@pytest.mark.parametrize("f16", [False, True])
+def test_warp_box_leaves_no_trace(f16):
+    """The warp computes only the voxels clipped rays can sample, so cells
+    outside that box keep values of earlier evaluations (other w, other
+    layout).  Every evaluation of a sequence that grows and shrinks the box
+    and switches between the x- and y-fastest layouts equals, bit for bit,
+    the same evaluation in a fresh context."""
+    L = _lib()
+    g, f0, mean, U = _blob_case(False)
+    f0_t, _ = rounded(f0, torch.float32)
+    mean_t, _ = rounded(mean, torch.float32)
+    U_t, _ = rounded(U, torch.float32)
+    dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV))
+    dt = torch.float16 if f16 else torch.float32
+    geoms = [S.Geom(math.radians(a), 96, 80, 2.6, 2.6, 2.0) for a in (71.0, 88.0)]
+    rng = np.random.default_rng(9)
+    ys = [torch.tensor(rng.uniform(0.0, 1.0, (G.nv, G.nu)), dtype=torch.float32, device=DEV)
+          for G in geoms]
+    seq = [([-90.0, 60.0], 0), ([0.0, 0.0], 0), ([40.0, -25.0], 1), ([0.0, 0.0], 1),
+           ([-90.0, 60.0], 1), ([3.0, -2.0], 0)]
+    ctx = L.Context(g, dm, f0_t.to(DEV), image_dtype=dt)
+    for w, gi in seq:
+        J, grad = ctx.cost_grad(ys[gi], geoms[gi], w, 0.8, 0.1)
+        fresh = L.Context(g, dm, f0_t.to(DEV), image_dtype=dt)
+        Jf, gradf = fresh.cost_grad(ys[gi], geoms[gi], w, 0.8, 0.1)
+        fresh.close()
+        assert J == Jf and list(grad) == list(gradf), (w, gi, J, Jf, grad, gradf)
+    ctx.close()
+
+
 def test_solve_with_given_first_step(tiny_case):
     """opts.mu0 replaces step0 / |g_0| for the first trial, on both sides."""
     L = _lib()
