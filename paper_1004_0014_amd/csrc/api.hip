@@ -321,28 +321,87 @@ pcr_status compute_support(const pcr_grid& g, const pcr_model& m, pcr_dtype f0_d
                            const void* f0, int device, hipStream_t s, Support* out)
 {
     const int rows = 3 + 3 * m.K;   // then one more: max |f0|
+    const int nz = g.n[2];
+    const size_t sl_bytes = ((size_t)8 * nz * sizeof(int) + 255) / 256 * 256;
     DevBuf d;
-    PCR_TRY(d.ensure(64 + (rows + 1) * sizeof(float), device, s));
-    int box[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+    PCR_TRY(d.ensure(sl_bytes + (rows + 1) * sizeof(float), device, s));
+    std::vector<int> sl((size_t)8 * nz);
+    for (size_t e = 0; e < sl.size(); ++e) sl[e] = (e & 1) ? INT_MIN : INT_MAX;
     float mx[28] = {0};
-    float* dmx = (float*)((char*)d.p + 64);
-    HIP_TRY(hipMemcpyAsync(d.p, box, sizeof box, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dmx, mx, (rows + 1) * sizeof(float), hipMemcpyHostToDevice, s));
-    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
-    HIP_TRY(launch_support(f0_dtype, g, f0, (int*)d.p, s));
-    HIP_TRY(launch_absmax_rows(m.storage, m.mean, N, 3, dmx, s));
-    HIP_TRY(launch_absmax_rows(m.storage, m.U, N, 3 * m.K, dmx + 3, s));
-    HIP_TRY(launch_absmax_rows(f0_dtype, f0, N, 1, dmx + rows, s));
-    HIP_TRY(hipMemcpyAsync(box, d.p, sizeof box, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(mx, dmx, (rows + 1) * sizeof(float), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    float* dmx = (float*)((char*)d.p + sl_bytes);
+    auto fin = [&](pcr_status e) {
+        d.release();
+        return e;
+    };
+    const size_t N = (size_t)g.n[0] * g.n[1] * nz;
+    hipError_t he = hipMemcpyAsync(d.p, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(dmx, mx, (rows + 1) * sizeof(float), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = launch_support(f0_dtype, g, f0, (int*)d.p, s);
+    if (he == hipSuccess) he = launch_absmax_rows(m.storage, m.mean, N, 3, dmx, s);
+    if (he == hipSuccess) he = launch_absmax_rows(m.storage, m.U, N, 3 * m.K, dmx + 3, s);
+    if (he == hipSuccess) he = launch_absmax_rows(f0_dtype, f0, N, 1, dmx + rows, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(sl.data(), d.p, sl.size() * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(mx, dmx, (rows + 1) * sizeof(float), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return fin(fail(PCR_EDEVICE, "support pass: %s", hipGetErrorString(he)));
+    // the box: the union of the slices
     for (int a = 0; a < 3; ++a) {
-        out->lo[a] = box[a];
-        out->hi[a] = box[3 + a];
+        out->lo[a] = INT_MAX;
+        out->hi[a] = INT_MIN;
+    }
+    for (int z = 0; z < nz; ++z) {
+        const int* q = &sl[(size_t)8 * z];
+        if (q[0] > q[1]) continue;
+        out->lo[0] = std::min(out->lo[0], q[0]);
+        out->hi[0] = std::max(out->hi[0], q[1]);
+        out->lo[1] = std::min(out->lo[1], q[2]);
+        out->hi[1] = std::max(out->hi[1], q[3]);
+        out->lo[2] = std::min(out->lo[2], z);
+        out->hi[2] = std::max(out->hi[2], z);
+    }
+    for (int a = 0; a < 3; ++a) {
         out->mmax[a] = mx[a];
         for (int k = 0; k < 8; ++k) out->umax[k][a] = k < m.K ? mx[3 + 3 * k + a] : 0.0;
     }
     out->f0max = mx[rows];
+    // slabs of at most 16 per volume, at least 4 slices thick; a ray meets
+    // those within its z range plus the dilation
+    const int T = std::max(4, (nz + 15) / 16);
+    const int ns = (nz + T - 1) / T;
+    std::vector<float> tab((size_t)20 * ns);
+    for (int sb = 0; sb < ns; ++sb) {
+        int b[8] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+        int klo = INT_MAX, khi = INT_MIN;
+        for (int z = sb * T; z < std::min(nz, (sb + 1) * T); ++z) {
+            const int* q = &sl[(size_t)8 * z];
+            if (q[0] > q[1]) continue;
+            for (int c = 0; c < 4; ++c) {
+                b[2 * c] = std::min(b[2 * c], q[2 * c]);
+                b[2 * c + 1] = std::max(b[2 * c + 1], q[2 * c + 1]);
+            }
+            klo = std::min(klo, z);
+            khi = std::max(khi, z);
+        }
+        float* t = &tab[(size_t)10 * sb];            // x-fastest order (i = x)
+        float* u = &tab[(size_t)10 * (ns + sb)];     // y-fastest order (i = y)
+        if (klo > khi) {
+            for (int c = 0; c < 10; ++c) t[c] = u[c] = 0.0f;
+            t[8] = u[8] = 1.0f;   // empty: k lo > k hi
+            continue;
+        }
+        const float v[10] = {(float)b[0], (float)b[1], (float)b[2], (float)b[3], (float)b[4],
+                             (float)b[5], (float)b[6], (float)b[7], (float)klo, (float)khi};
+        for (int c = 0; c < 10; ++c) t[c] = v[c];
+        const float w[10] = {v[2], v[3], v[0], v[1], v[4], v[5], -v[7], -v[6], v[8], v[9]};
+        for (int c = 0; c < 10; ++c) u[c] = w[c];
+    }
+    d.release();
+    PCR_TRY(out->slab_buf.ensure(tab.size() * sizeof(float), device, s));
+    HIP_TRY(hipMemcpyAsync(out->slab_buf.p, tab.data(), tab.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->nslab = ns;
+    out->slab_t = T;
     out->valid = true;
     return PCR_OK;
 }
@@ -365,6 +424,19 @@ void half_scales(const Support& sp, const pcr_grid& g, int K, float hs[8])
     }
 }
 
+// Half-widths (voxels) of the dilation: the displacement bound along each
+// axis, with room for the FP32 rounding of the displacements, plus 2.5 cells
+// (one for the trilinear taps of f0, one for those of the sample, a half
+// for rounding).
+static void dilation(const Support& sp, const pcr_grid& g, int K, const double* w_eff, double h[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double d = sp.mmax[a];
+        for (int k = 0; k < K; ++k) d += std::fabs(w_eff[k]) * sp.umax[k][a];
+        h[a] = d * 1.0001 / g.spacing_mm[a] + 2.5;
+    }
+}
+
 void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
               double clo[3], double chi[3])
 {
@@ -374,18 +446,30 @@ void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, 
             return;
         }
     }
+    double h[3];
+    dilation(sp, g, K, w_eff, h);
     for (int a = 0; a < 3; ++a) {
-        double d = sp.mmax[a];
-        for (int k = 0; k < K; ++k) d += std::fabs(w_eff[k]) * sp.umax[k][a];
-        // in voxels, with room for the FP32 rounding of the displacements
-        d = d * 1.0001 / g.spacing_mm[a];
-        clo[a] = std::max(-1.0, (double)sp.lo[a] - d - 2.5);
-        chi[a] = std::min((double)g.n[a], (double)sp.hi[a] + d + 2.5);
+        clo[a] = std::max(-1.0, (double)sp.lo[a] - h[a]);
+        chi[a] = std::min((double)g.n[a], (double)sp.hi[a] + h[a]);
     }
     if (swap_xy) {
         std::swap(clo[0], clo[1]);
         std::swap(chi[0], chi[1]);
     }
+}
+
+void clip_geom(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
+               RayGeom& rg)
+{
+    clip_box(sp, g, K, w_eff, swap_xy, rg.clo, rg.chi);
+    if (sp.lo[0] > sp.hi[0] || sp.nslab == 0 || !sp.slab_buf.p) return;
+    double h[3];
+    dilation(sp, g, K, w_eff, h);
+    if (swap_xy) std::swap(h[0], h[1]);
+    rg.slabs = (const float*)sp.slab_buf.p + (swap_xy ? 10 * sp.nslab : 0);
+    rg.nslab = sp.nslab;
+    rg.slab_t = sp.slab_t;
+    for (int a = 0; a < 3; ++a) rg.h[a] = (float)h[a];
 }
 
 void warp_box(const RayGeom& g, const pcr_grid& grid, int box[6])
@@ -411,8 +495,8 @@ pcr_status Evaluator::enqueue_eval(const double* w)
     int vbox[6];
     const int* box = nullptr;
     if (sup && sup->valid) {
-        clip_box(*sup, *grid, K, w_eff, sc->Lc.yfast, gc.clo, gc.chi);
-        clip_box(*sup, *grid, K, w_eff, false, g1.clo, g1.chi);
+        clip_geom(*sup, *grid, K, w_eff, sc->Lc.yfast, gc);
+        clip_geom(*sup, *grid, K, w_eff, false, g1);
         warp_box(g1, *grid, vbox);
         box = vbox;
     }
@@ -756,7 +840,11 @@ struct pcr_ctx {
     Scratch sc;
     Support sup;   // computed on the first evaluation
     bool image_f16 = false;
-    ~pcr_ctx() { sc.release(); }
+    ~pcr_ctx()
+    {
+        sc.release();
+        sup.release();
+    }
 };
 
 extern "C" {

@@ -152,12 +152,20 @@ struct Scratch {
 // box dilated by the displacement and one cell, and a ray sample contributes
 // nothing outside it dilated by one more cell.  The march clips rays to this
 // box: the samples it skips are exactly zero, the sample grid is unchanged.
+//
+// Within the box, rays are clipped further to slabs of slab_t slices: per
+// slab an octagon in (i, j) (bounds on i, j, i + j, i - j) and a range in k
+// holding its nonzero voxels, dilated the same way (slab_buf: the FP32
+// tables of RayGeom::slabs, x-fastest axis order then y-fastest).
 struct Support {
     bool valid = false;
     int lo[3], hi[3];        // nonzero f0 voxels (lo > hi: none)
     double mmax[3];          // max |mean_a| (mm)
     double umax[8][3];       // max |U_k,a| of the stored fields
     double f0max;            // max |f0|
+    int nslab = 0, slab_t = 1;
+    DevBuf slab_buf;         // owned; release() frees it
+    void release() { slab_buf.release(); }
 };
 // FP16 channel scales (powers of two): f is bounded by max|f0| and h_k by
 // 2 max|f0| sum_a max|U_k,a| / s_a (each partial derivative of the
@@ -168,6 +176,10 @@ pcr_status compute_support(const pcr_grid& g, const pcr_model& m, pcr_dtype f0_d
 // Ray clip box (index space; x and y swapped for the y-fastest layout).
 void clip_box(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
               double clo[3], double chi[3]);
+// Clips a ray geometry (built with the same swap_xy) to the box and slabs
+// for the displacements of w_eff.
+void clip_geom(const Support& sp, const pcr_grid& g, int K, const double* w_eff, bool swap_xy,
+               RayGeom& rg);
 // Voxels {lo x, lo y, lo z, hi x, hi y, hi z} (hi exclusive) whose cells the
 // samples of rays clipped to g's box can read (grid axis order): the warp
 // computes only these, since no other cell is sampled.

@@ -374,14 +374,90 @@ struct RaySeg {
     int count;       // samples in the segment
 };
 
-// Sample range of ray (iu, iv) on the global grid t = n dt, clipped to the
-// support box [-1, n_a] of the interpolant (widened by one sample at each
-// end: samples outside the support are clamped onto zero cells), then split
-// into `seg` equal segments.  FP64, once per ray.
-template <typename R>
-__device__ __forceinline__ RaySeg<R> ray_segment(const RayGeom& g, int iu, int iv, int seg, int sid)
+// One direction of the slab tests along a ray: the coordinate o + t d,
+// with 1 / d and the offsets that fold the dilation into one FMA per bound:
+// t = lo * inv + nlo is where the coordinate reaches lo - h, t = hi * inv + nhi
+// where it reaches hi + h.  |d| < 1e-20: the coordinate is taken as
+// constant (it moves by < 1e-16 index units over any ray; 1 / d would
+// overflow the offsets).
+struct SlabAxis {
+    float o, inv, nlo, nhi;
+    bool flat;
+    __device__ __forceinline__ void init(float o_, float d, float h)
+    {
+        o = o_;
+        flat = fabsf(d) < 1e-20f;
+        inv = flat ? 0.0f : 1.0f / d;
+        nlo = -(o + h) * inv;
+        nhi = (h - o) * inv;
+    }
+    __device__ __forceinline__ void clip(float lo, float hi, float h, float& ta, float& tb) const
+    {
+        if (!flat) {
+            const float t1 = fmaf(lo, inv, nlo), t2 = fmaf(hi, inv, nhi);
+            ta = fmaxf(ta, fminf(t1, t2));
+            tb = fminf(tb, fmaxf(t1, t2));
+        } else if (!(o >= lo - h && o <= hi + h)) {
+            ta = INFINITY;
+        }
+    }
+};
+
+// Narrows the box segment [tmin, tmax] of a ray (direction dq, index units
+// per mm) to the hull of its intersections with the dilated slab regions:
+// outside every one of them all of the ray's samples are exactly zero.  The
+// bounds are evaluated in FP32: where a constraint binds, the rounding moves
+// the cut point by ~1e-4 index units along that constraint's own axis,
+// against the half-cell slack of the dilation.
+__device__ __forceinline__ void refine_by_slabs(const RayGeom& g, const double dq[3], double& tmin,
+                                                double& tmax)
 {
-    RaySeg<R> r;
+    const double za = g.qs[2] + tmin * dq[2], zb = g.qs[2] + tmax * dq[2];
+    // slab s (slices sT .. sT + T - 1) reaches k in [sT - h, sT + T - 1 + h]
+    const float zlo = (float)fmin(za, zb) - g.h[2], zhi = (float)fmax(za, zb) + g.h[2];
+    const float T = (float)g.slab_t, lim = (float)g.nslab + 2.0f;
+    const int s0 = max(0, (int)floorf(fminf(fmaxf((zlo + 1.0f) / T - 1.0f, -2.0f), lim)) - 1);
+    const int s1 = min(g.nslab - 1, (int)floorf(fminf(fmaxf(zhi / T, -2.0f), lim)));
+    const float o0 = (float)g.qs[0], o1 = (float)g.qs[1], d0 = (float)dq[0], d1 = (float)dq[1];
+    const float hd = g.h[0] + g.h[1];
+    SlabAxis ax, ay, ap, am, az;
+    ax.init(o0, d0, g.h[0]);
+    ay.init(o1, d1, g.h[1]);
+    ap.init(o0 + o1, d0 + d1, hd);
+    am.init(o0 - o1, d0 - d1, hd);
+    az.init((float)g.qs[2], (float)dq[2], g.h[2]);
+    float tin = INFINITY, tout = -INFINITY;
+    for (int s = s0; s <= s1; ++s) {
+        const float* b = g.slabs + 10 * s;
+        if (b[8] > b[9]) continue;   // no nonzero voxel in this slab
+        float ta = -INFINITY, tb = INFINITY;
+        az.clip(b[8], b[9], g.h[2], ta, tb);
+        ax.clip(b[0], b[1], g.h[0], ta, tb);
+        ay.clip(b[2], b[3], g.h[1], ta, tb);
+        ap.clip(b[4], b[5], hd, ta, tb);
+        am.clip(b[6], b[7], hd, ta, tb);
+        if (ta <= tb) {
+            tin = fminf(tin, ta);
+            tout = fmaxf(tout, tb);
+        }
+    }
+    tmin = fmax(tmin, (double)tin);
+    tmax = fmin(tmax, (double)tout);
+}
+
+// Global sample range [n0, n1] of ray (iu, iv) (n1 < n0: none) on the grid
+// t = n dt, clipped to the box (at most the support [-1, n_a] of the
+// interpolant) and the slabs, widened by one sample at each end (samples
+// outside the support are clamped onto zero cells), and the ray's direction
+// (index units per mm).  FP64, once per ray.
+struct RayRange {
+    int n0, n1;
+    double dq[3];
+};
+
+__device__ __forceinline__ RayRange ray_range(const RayGeom& g, int iu, int iv)
+{
+    RayRange r;
     double u = g.u0 + iu * g.du, v = g.v0 + iv * g.dv;
     double D[3], L2 = 0.0;
 #pragma unroll
@@ -391,38 +467,48 @@ __device__ __forceinline__ RaySeg<R> ray_segment(const RayGeom& g, int iu, int i
         L2 += w * w;
     }
     double L = sqrt(L2);
-    double tmin = 0.0, tmax = L, dq[3];
+    double tmin = 0.0, tmax = L;
     bool hit = L > 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        dq[a] = D[a] / L;
-        if (dq[a] != 0.0) {
-            double t1 = (g.clo[a] - g.qs[a]) / dq[a], t2 = (g.chi[a] - g.qs[a]) / dq[a];
+        r.dq[a] = hit ? D[a] / L : 0.0;
+        if (r.dq[a] != 0.0) {
+            double t1 = (g.clo[a] - g.qs[a]) / r.dq[a], t2 = (g.chi[a] - g.qs[a]) / r.dq[a];
             tmin = fmax(tmin, fmin(t1, t2));
             tmax = fmin(tmax, fmax(t1, t2));
         } else if (!(g.qs[a] > g.clo[a] && g.qs[a] < g.chi[a])) {
             hit = false;
         }
     }
-    r.count = 0;
-    if (!hit || !(tmin <= tmax)) {
-        r.q0[0] = r.q0[1] = r.q0[2] = (R)0;
-        r.dq[0] = r.dq[1] = r.dq[2] = (R)0;
-        return r;
-    }
+    if (g.slabs && hit && tmin <= tmax) refine_by_slabs(g, r.dq, tmin, tmax);
+    r.n0 = 0;
+    r.n1 = -1;
+    if (!hit || !(tmin <= tmax)) return r;
     long nlast = (long)floor(L / g.dt);
     long n0 = (long)ceil(tmin / g.dt) - 1, n1 = (long)floor(tmax / g.dt) + 1;
     if (n0 < 0) n0 = 0;
     if (n1 > nlast) n1 = nlast;
-    long cnt = n1 - n0 + 1;
-    if (cnt < 0) cnt = 0;
+    if (n1 >= n0) {
+        r.n0 = (int)n0;
+        r.n1 = (int)n1;
+    }
+    return r;
+}
+
+// The ray's range split into `seg` equal segments: segment `sid`.
+template <typename R>
+__device__ __forceinline__ RaySeg<R> ray_segment(const RayGeom& g, int iu, int iv, int seg, int sid)
+{
+    RaySeg<R> r;
+    const RayRange rr = ray_range(g, iu, iv);
+    const long cnt = rr.n1 >= rr.n0 ? (long)rr.n1 - rr.n0 + 1 : 0;
     long m0 = cnt * sid / seg, m1 = cnt * (sid + 1) / seg;
     r.count = (int)(m1 - m0);
-    double t0 = (double)(n0 + m0) * g.dt;
+    double t0 = (double)(rr.n0 + m0) * g.dt;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        r.q0[a] = (R)(g.qs[a] + t0 * dq[a]);
-        r.dq[a] = (R)(g.dt * dq[a]);
+        r.q0[a] = (R)(g.qs[a] + t0 * rr.dq[a]);
+        r.dq[a] = (R)(g.dt * rr.dq[a]);
     }
     return r;
 }
@@ -642,7 +728,7 @@ struct MarchArgs {
 };
 
 template <int C, bool BUF, bool H>
-__global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 8 : 1))) k_march_f32(MarchArgs A)
 {
     static_assert(!(H && BUF), "FP16 cells use global loads");
     constexpr int CB = (H ? 2 : 4) * C;   // bytes per cell
@@ -659,20 +745,62 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
     int nsamp = 0;
-    if (valid) {
-        RaySeg<float> rs = ray_segment<float>(g, iu, iv, A.ms.seg, sid);
-        nsamp = rs.count;
+    // The wave marches the union of its rays' sample ranges in step: at each
+    // iteration all its lanes sit at the same global sample index n (t = n
+    // dt), so neighbouring rays read neighbouring cells and share cache
+    // lines; a lane skips the indices outside its own ray's range.  The waves
+    // holding the same 64 rays (one per segment) split the union into equal
+    // parts, so each sample of a ray is taken exactly once.
+    RayRange rr;
+    rr.n0 = 0;
+    rr.n1 = -1;
+    rr.dq[0] = rr.dq[1] = rr.dq[2] = 0.0;
+    // LDS: first the block's ray set-ups, then the segments' partial sums
+    constexpr int kSmem = 256 * C * 4 > 128 * (int)sizeof(RayRange) ? 256 * C * 4 : 128 * (int)sizeof(RayRange);
+    __shared__ __align__(16) char smem[kSmem];
+    if (A.ms.seg > 1) {
+        // the segment-0 waves set up the block's rays, the others read them
+        RayRange* rbuf = (RayRange*)smem;
+        if (sid == 0) {
+            if (valid) rr = ray_range(g, iu, iv);
+            rbuf[rloc] = rr;
+        }
+        __syncthreads();
+        rr = rbuf[rloc];
+        __syncthreads();   // before the buffer is reused for the partial sums
+    } else if (valid) {
+        rr = ray_range(g, iu, iv);
+    }
+    int N0 = rr.n1 >= rr.n0 ? rr.n0 : INT_MAX, N1 = rr.n1 >= rr.n0 ? rr.n1 : INT_MIN;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        N0 = min(N0, __shfl_xor(N0, o));
+        N1 = max(N1, __shfl_xor(N1, o));
+    }
+    N0 = __builtin_amdgcn_readfirstlane(N0);
+    N1 = __builtin_amdgcn_readfirstlane(N1);
+    if (N0 <= N1) {
+        const long span = (long)N1 - N0 + 1;
+        const int na = __builtin_amdgcn_readfirstlane(N0 + (int)(span * sid / A.ms.seg));
+        const int nb = __builtin_amdgcn_readfirstlane(N0 + (int)(span * (sid + 1) / A.ms.seg));
         // padded index space: cell i+1 holds voxel i, so q + 1 >= 0 after the
         // clamp and truncation is the floor
-        const float q0x = rs.q0[0] + 1.f, q0y = rs.q0[1] + 1.f, q0z = rs.q0[2] + 1.f;
+        const double ta = (double)na * g.dt;
+        const float q0x = (float)(g.qs[0] + ta * rr.dq[0]) + 1.f;
+        const float q0y = (float)(g.qs[1] + ta * rr.dq[1]) + 1.f;
+        const float q0z = (float)(g.qs[2] + ta * rr.dq[2]) + 1.f;
+        const float dqx = (float)(g.dt * rr.dq[0]), dqy = (float)(g.dt * rr.dq[1]),
+                    dqz = (float)(g.dt * rr.dq[2]);
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.vol), (short)0, A.vol_bytes, 0x00020000);
         const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs;
-        for (int m = 0; m < rs.count; ++m) {
-            const float fm = (float)m;
-            float qx = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[0], q0x), 0.f, A.fn1[0]);
-            float qy = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[1], q0y), 0.f, A.fn1[1]);
-            float qz = __builtin_amdgcn_fmed3f(fmaf(fm, rs.dq[2], q0z), 0.f, A.fn1[2]);
+        for (int n = na; n < nb; ++n) {
+            if (n < rr.n0 || n > rr.n1) continue;
+            ++nsamp;
+            const float fm = (float)(n - na);
+            float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
+            float qy = __builtin_amdgcn_fmed3f(fmaf(fm, dqy, q0y), 0.f, A.fn1[1]);
+            float qz = __builtin_amdgcn_fmed3f(fmaf(fm, dqz, q0z), 0.f, A.fn1[2]);
             const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
             const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
                         az = __builtin_amdgcn_fractf(qz);
@@ -716,7 +844,7 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
         }
     }
     if (A.ms.seg > 1) {
-        __shared__ float segbuf[256 * C];
+        float* segbuf = (float*)smem;
 #pragma unroll
         for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
         __syncthreads();
@@ -762,47 +890,53 @@ __global__ void __launch_bounds__(256) k_march_f32(MarchArgs A)
 }
 
 // ------------------------------------------------------------ support --
-// Index box of the nonzero voxels of an image: box = (min x, min y, min z,
-// max x, max y, max z), combined into `box` with atomics (the caller sets
-// it to (INT_MAX x3, INT_MIN x3) first).  NaN counts as nonzero.
+// Bounds of the nonzero voxels of each slice of an image (see
+// launch_support), combined with atomics.  NaN counts as nonzero.
 template <typename F>
 __global__ void __launch_bounds__(256) k_support(const F* __restrict__ f0, int nx, int ny, int nz,
-                                                 int* __restrict__ box)
+                                                 int* __restrict__ sl)
 {
-    __shared__ int sb[6];
-    if (threadIdx.x < 6) sb[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
-    __syncthreads();
-    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    __shared__ int sb[8];
     const int nxy = nx * ny;
     for (int z = blockIdx.y; z < nz; z += gridDim.y) {
+        if (threadIdx.x < 8) sb[threadIdx.x] = (threadIdx.x & 1) ? INT_MIN : INT_MAX;
+        __syncthreads();
+        int b[8] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
         for (int e = blockIdx.x * 256 + threadIdx.x; e < nxy; e += gridDim.x * 256) {
             const float v = widen<float>(f0[(size_t)z * nxy + e]);
             if (!(v == 0.0f)) {
                 const int x = e % nx, y = e / nx;
-                lo[0] = min(lo[0], x); hi[0] = max(hi[0], x);
-                lo[1] = min(lo[1], y); hi[1] = max(hi[1], y);
-                lo[2] = min(lo[2], z); hi[2] = max(hi[2], z);
+                const int q[4] = {x, y, x + y, x - y};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    b[2 * c] = min(b[2 * c], q[c]);
+                    b[2 * c + 1] = max(b[2 * c + 1], q[c]);
+                }
             }
         }
-    }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 4; ++c) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lo[a] = min(lo[a], __shfl_xor(lo[a], o));
-            hi[a] = max(hi[a], __shfl_xor(hi[a], o));
+            for (int o = 32; o > 0; o >>= 1) {
+                b[2 * c] = min(b[2 * c], __shfl_xor(b[2 * c], o));
+                b[2 * c + 1] = max(b[2 * c + 1], __shfl_xor(b[2 * c + 1], o));
+            }
         }
-    }
-    if ((threadIdx.x & 63) == 0) {
+        if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&sb[a], lo[a]);
-            atomicMax(&sb[3 + a], hi[a]);
+            for (int c = 0; c < 4; ++c) {
+                atomicMin(&sb[2 * c], b[2 * c]);
+                atomicMax(&sb[2 * c + 1], b[2 * c + 1]);
+            }
         }
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            int* t = sl + (size_t)8 * z + threadIdx.x;
+            if (threadIdx.x & 1) atomicMax(t, sb[threadIdx.x]);
+            else atomicMin(t, sb[threadIdx.x]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < 3) atomicMin(&box[threadIdx.x], sb[threadIdx.x]);
-    else if (threadIdx.x < 6) atomicMax(&box[threadIdx.x], sb[threadIdx.x]);
 }
 
 // out[row] = max |a[row][i]| over i < n, combined with atomics on the bit
@@ -1689,14 +1823,14 @@ hipError_t launch_warp_adjoint(pcr_dtype compute, const pcr_grid& g, const void*
     return hipGetLastError();
 }
 
-hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* box,
+hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* sl,
                           hipStream_t s)
 {
     const long nxy = (long)g.n[0] * g.n[1];
-    const unsigned bx = (unsigned)std::min<long>((nxy + 255) / 256, 16);
-    const unsigned bz = (unsigned)std::min(g.n[2], 64);
+    const unsigned bx = (unsigned)std::min<long>((nxy + 2047) / 2048, 32);
+    const unsigned bz = (unsigned)std::min(g.n[2], 65535);
     PCR_DISPATCH_S(f0_dtype, F,
-        k_support<F><<<dim3(bx, bz), 256, 0, s>>>((const F*)f0, g.n[0], g.n[1], g.n[2], box));
+        k_support<F><<<dim3(bx, bz), 256, 0, s>>>((const F*)f0, g.n[0], g.n[1], g.n[2], sl));
     return hipGetLastError();
 }
 

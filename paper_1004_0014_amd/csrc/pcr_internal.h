@@ -66,6 +66,15 @@ struct RayGeom {
     double du, dv;       // pixel pitch (mm)
     double dt;           // sample spacing (mm)
     int nu, nv;
+    // Tighter clipping within the box (null: none): per slab of slab_t
+    // slices, 10 floats {i lo, hi; j lo, hi; i+j lo, hi; i-j lo, hi; k lo, hi}
+    // bound the nonzero voxels of the reference image (index space, this
+    // geometry's axis order; lo > hi: empty slab).  Dilated by h (i, j, k),
+    // and by h_i + h_j along the diagonals, they bound where a sample can be
+    // nonzero; a ray is clipped to the hull of the slabs it meets.
+    const float* slabs = nullptr;
+    int nslab = 0, slab_t = 1;
+    float h[3] = {0.0f, 0.0f, 0.0f};
 };
 // swap_xy: express the geometry in (y, x, z) index order (y-fastest layout).
 RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy = false);
@@ -117,9 +126,10 @@ hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const Ray
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
                         double* partials, double* moments, unsigned* counter, hipStream_t s);
 // Fixed-order final sum of per-block partials: out[m] for m < nm.
-// Index box of the nonzero voxels of f0 into box[6] (min xyz, max xyz; the
-// caller initialises it to INT_MAX x3, INT_MIN x3).
-hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* box,
+// Per slice z of f0, bounds of its nonzero voxels (i, j): sl[8 z ..] =
+// {min i, max i, min j, max j, min i+j, max i+j, min i-j, max i-j}; the
+// caller initialises every (min, max) pair to (INT_MAX, INT_MIN).
+hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0, int* sl,
                           hipStream_t s);
 // out[r] = max_i |a[r][i]| for `rows` rows of n values (out zeroed by the caller).
 hipError_t launch_absmax_rows(pcr_dtype dt, const void* a, size_t n, int rows, float* out,

@@ -41,6 +41,7 @@ struct StreamDev {
         f0.release();
         mean.release();
         U.release();
+        sup.release();
     }
 };
 
