@@ -282,7 +282,7 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     }
     sc->L1 = make_pad(*grid, 1);
     rgc = make_ray_geom(*grid, G, yfast);
-    msc = choose_march_shape(rgc, yfast);
+    msc = choose_march_shape(rgc);
     blocksc = march_blocks(rgc, msc);
     const int dev = sc->device;
     if (mode == PCR_GRAD_FUSED) {
@@ -509,7 +509,7 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         {
             PROF(MARCH, s);
             HIP_TRY(launch_march(compute, sc->Lc, kc, gc, msc, sc->volc.p, y, nullptr,
-                                 (double*)sc->partials.p, mom, nullptr, s));
+                                 (double*)sc->partials.p, mom, s));
         }
     } else {
         {
@@ -520,7 +520,7 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         {
             PROF(MARCH, s);
             HIP_TRY(launch_march(compute, sc->L1, 1, g1, ms, sc->vol1.p, y, sc->p.p,
-                                 (double*)sc->partials.p, mom, nullptr, s));
+                                 (double*)sc->partials.p, mom, s));
         }
     }
     HIP_TRY(hipMemcpyAsync(sc->host.p, mom, (n_moments(kc) + 1) * sizeof(double), hipMemcpyDeviceToHost,
@@ -562,7 +562,7 @@ pcr_status Evaluator::grad_adjoint(const double* w, double a, double b, double* 
     }
     {
         PROF(REDUCE, s);
-        HIP_TRY(launch_reduce((const double*)sc->partials.p, contract_blocks(*grid), 8, K,
+        HIP_TRY(launch_reduce((const double*)sc->partials.p, contract_blocks(*grid), K,
                               (double*)sc->moments.p, s));
     }
     HIP_TRY(hipMemcpyAsync(sc->host.p, sc->moments.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -729,7 +729,7 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     RayGeom rg = make_ray_geom(*grid, *geom);
     MarchShape ms = choose_march_shape(rg);
     PROF(MARCH, s);
-    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, nullptr, s));
+    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, s));
     return PCR_OK;
 }
 
@@ -774,7 +774,7 @@ pcr_status pcr_warp_contract(const pcr_grid* grid, const pcr_model* model, pcr_d
     }
     {
         PROF(REDUCE, s);
-        HIP_TRY(launch_reduce(part, nb, 8, model->K, out, s));
+        HIP_TRY(launch_reduce(part, nb, model->K, out, s));
     }
     HIP_TRY(hipMemcpyAsync(tls.host.p, out, model->K * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -73,9 +73,9 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Block (256 threads = 4 waves) sum of NM doubles per thread; thread t < nm
-// writes dst[t].  Fixed order: wave tree, then waves 0..3.
+// writes dst[t * stride].  Fixed order: wave tree, then waves 0..3.
 template <int NM>
-__device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double* dst)
+__device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double* dst, int stride)
 {
     __shared__ double red[4][NM];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -90,60 +90,34 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
         s += red[1][threadIdx.x];
         s += red[2][threadIdx.x];
         s += red[3][threadIdx.x];
-        dst[threadIdx.x] = s;
+        dst[(size_t)threadIdx.x * stride] = s;
     }
 }
 
-// Sum of the blocks' records: record b is part[b * NS .. b * NS + NS).
-// out[0..nm) = sums of slots 0..nm-1; with extra >= 0 also out[nm] = the sum
-// of slot `extra`.  Thread t loads whole records t, t + 512, ... (NS
-// independent loads each, so the latency is paid once per record, not once
-// per value) and adds them in order; the 512 partial records are then
-// combined in a fixed tree (wave shuffles, then the 8 waves in order):
-// deterministic.
-template <int NS>
-__global__ void __launch_bounds__(512) k_reduce(const double* __restrict__ part, int nblocks, int nm,
-                                                int extra, double* __restrict__ out)
+// Sum over the blocks of their partial sums, stored slot-major: part[m *
+// nblocks + b] is slot m of block b.  out[0..nm) = sums of slots 0..nm-1;
+// with extra >= 0 also out[nm] = the sum of slot `extra`.  One wave per
+// output: lane l adds blocks l, l + 64, ... in order (coalesced loads), then
+// a fixed shuffle tree: deterministic.
+__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part, int nblocks, int nm,
+                                                 int extra, double* __restrict__ out)
 {
-    __shared__ double wsum[8][NS];
-    double s[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) s[m] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 512) {
-        const double* r = part + (size_t)b * NS;
-        double v[NS];
-#pragma unroll
-        for (int m = 0; m < NS; ++m) v[m] = r[m];
-#pragma unroll
-        for (int m = 0; m < NS; ++m) s[m] += v[m];
-    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-        const double t = wave_sum(s[m]);
-        if (lane == 0) wsum[wv][m] = t;
-    }
-    __syncthreads();
     const int nout = nm + (extra >= 0 ? 1 : 0);
-    if ((int)threadIdx.x < nout) {
-        const int slot = (int)threadIdx.x < nm ? (int)threadIdx.x : extra;
-        double t = wsum[0][slot];
-        for (int w = 1; w < 8; ++w) t += wsum[w][slot];
-        out[threadIdx.x] = t;
+    for (int o = wv; o < nout; o += 16) {
+        const double* r = part + (size_t)(o < nm ? o : extra) * nblocks;
+        double s = 0.0;
+#pragma unroll 8
+        for (int b = lane; b < nblocks; b += 64) s += r[b];
+        s = wave_sum(s);
+        if (lane == 0) out[o] = s;
     }
 }
 
-static hipError_t run_reduce(const double* part, int nblocks, int stride, int nm, int extra,
-                             double* out, hipStream_t s)
+static hipError_t run_reduce(const double* part, int nblocks, int nm, int extra, double* out,
+                             hipStream_t s)
 {
-    switch (stride) {
-    case 6: k_reduce<6><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
-    case 8: k_reduce<8><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
-    case 9: k_reduce<9><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
-    case 15: k_reduce<15><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
-    case 27: k_reduce<27><<<1, 512, 0, s>>>(part, nblocks, nm, extra, out); break;
-    default: return hipErrorInvalidValue;
-    }
+    k_reduce<<<1, 1024, 0, s>>>(part, nblocks, nm, extra, out);
     return hipGetLastError();
 }
 
@@ -609,7 +583,7 @@ __global__ void __launch_bounds__(256) k_march(RayGeom g, MarchShape ms, int til
                 }
             }
         }
-        block_sum_store<NM + 1>(m, NM + 1, partials + (size_t)blockIdx.x * (NM + 1));
+        block_sum_store<NM + 1>(m, NM + 1, partials + blockIdx.x, (int)gridDim.x);
     }
 }
 
@@ -721,9 +695,8 @@ struct MarchArgs {
     int kc;                // channels used
     const float* y;        // measured projection (moments) or null
     float* p_out;          // projection out or null
-    double* partials;      // [blocks][NM] or null
+    double* partials;      // [NM][blocks] (slot-major) or null
     double* moments;       // final moments (last block) or null
-    unsigned* counter;     // last-block counter
     float ihs[8];          // FP16 cells: 1 / channel scale
 };
 
@@ -885,7 +858,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 }
             }
         }
-        block_sum_store<NM + 1>(mo, NM + 1, A.partials + (size_t)blockIdx.x * (NM + 1));
+        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x);
     }
 }
 
@@ -1198,7 +1171,7 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
 }
 
 // ---------------------------------------------------------- contraction --
-// partials[block][k] = sum_v g[v] * sum_a (1/s_a) dT[f0]/dq_a(q_v) u_k[a][v]
+// partials[k * blocks + block] = sum_v g[v] * sum_a (1/s_a) dT[f0]/dq_a(q_v) u_k[a][v]
 template <typename R, typename S, typename F>
 __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
                                                   const S* __restrict__ mean,
@@ -1255,7 +1228,8 @@ __global__ void __launch_bounds__(256) k_contract(const F* __restrict__ f0,
     int t = threadIdx.x + 64 * threadIdx.y;
     if (t < K) {
         size_t blk = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-        partials[blk * 8 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+        size_t nblk = (size_t)gridDim.x * gridDim.y * gridDim.z;
+        partials[t * nblk + blk] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
     }
 }
 
@@ -1455,21 +1429,16 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy)
     return r;
 }
 
-MarchShape choose_march_shape(const RayGeom& rg, bool yfast)
+MarchShape choose_march_shape(const RayGeom& rg)
 {
     MarchShape ms;
     long rays = (long)rg.nu * rg.nv;
-    if (yfast) {
-        // rays close to the x axis on the y-fastest layout: one thread per ray
-        ms.seg = 1;
-        ms.tile_u = 16;
-    } else {
-        // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays when they
-        // are few; tiles of 64 rays per wave as close to square in the volume
-        // as the split allows (4 x 16 with 4 segments, 8 x 8 with 2)
-        ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
-        ms.tile_u = ms.seg == 4 ? 4 : (ms.seg == 2 ? 8 : 16);
-    }
+    // aim for >= ~8 waves per SIMD on 1024 SIMDs: split rays into segments
+    // when they are few; each wave takes 4 (u) x 16 (v) rays, stepping
+    // through the union of their sample ranges together (measured best on
+    // both layouts)
+    ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
+    ms.tile_u = 4;
     // tuning overrides (launch-shape sweeps): PCR_MARCH_TILE_U in {4..64},
     // PCR_MARCH_SEG in {1, 2, 4}
     if (const char* e = std::getenv("PCR_MARCH_TILE_U")) {
@@ -1669,14 +1638,14 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     if (moments) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return run_reduce(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C), moments, s);
+        return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s);
     }
     return hipGetLastError();
 }
 
 static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
                             const void* padded, const void* y, void* p_out, double* partials,
-                            double* moments, unsigned* counter, hipStream_t s)
+                            double* moments, hipStream_t s)
 {
     MarchArgs A;
     A.g = rg;
@@ -1697,7 +1666,6 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.p_out = (float*)p_out;
     A.partials = moments ? partials : nullptr;
     A.moments = moments;
-    A.counter = counter;
     int blocks = march_blocks(rg, ms);
     const bool buf = ms.buffer_loads;
 #define PCR_MF(C)                                                                                 \
@@ -1718,24 +1686,23 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
 #undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
-    return run_reduce(partials, blocks, n_moments(L.C) + 1, n_moments(kc), n_moments(L.C), moments, s);
+    return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s);
 }
 
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, double* moments, unsigned* counter, hipStream_t s)
+                        double* partials, double* moments, hipStream_t s)
 {
     if (compute == PCR_F32)
-        return march_f32(L, kc, rg, ms, padded, y, p_out, partials, moments, counter, s);
+        return march_f32(L, kc, rg, ms, padded, y, p_out, partials, moments, s);
     if (compute == PCR_F64)
         return march_r<double>(L, kc, rg, ms, padded, y, p_out, partials, moments, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
-                         hipStream_t s)
+hipError_t launch_reduce(const double* partials, int nblocks, int nm, double* out, hipStream_t s)
 {
-    return run_reduce(partials, nblocks, stride, nm, -1, out, s);
+    return run_reduce(partials, nblocks, nm, -1, out, s);
 }
 
 hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeom& rg,

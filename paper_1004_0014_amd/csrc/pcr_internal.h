@@ -85,7 +85,7 @@ struct MarchShape {
     int seg;             // ray segments (threads) per ray: 1, 2 or 4
     bool buffer_loads;   // FP32 march: raw buffer loads (else global loads)
 };
-MarchShape choose_march_shape(const RayGeom& rg, bool yfast = false);
+MarchShape choose_march_shape(const RayGeom& rg);
 
 // Moments returned by a ray march over channels (f, h_1..h_K):
 //   0 sum y, 1 sum y^2, 2 sum p, 3 sum y p, 4 sum p^2,
@@ -121,10 +121,10 @@ hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padde
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Ray march over kc used channels of a padded image; writes p (may be null)
 // and, when moments != null, the detector moments (y required then; uses
-// `partials` [march_blocks][kMaxMoments] and the zero-initialised `counter`).
+// `partials`, room for march_blocks x kMaxMoments doubles).
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, double* moments, unsigned* counter, hipStream_t s);
+                        double* partials, double* moments, hipStream_t s);
 // Fixed-order final sum of per-block partials: out[m] for m < nm.
 // Per slice z of f0, bounds of its nonzero voxels (i, j): sl[8 z ..] =
 // {min i, max i, min j, max j, min i+j, max i+j, min i-j, max i-j}; the
@@ -134,14 +134,15 @@ hipError_t launch_support(pcr_dtype f0_dtype, const pcr_grid& g, const void* f0,
 // out[r] = max_i |a[r][i]| for `rows` rows of n values (out zeroed by the caller).
 hipError_t launch_absmax_rows(pcr_dtype dt, const void* a, size_t n, int rows, float* out,
                               hipStream_t s);
-hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nm, double* out,
-                         hipStream_t s);
+// out[m] = sum over blocks b of partials[m * nblocks + b] (slot-major), m < nm;
+// fixed order.
+hipError_t launch_reduce(const double* partials, int nblocks, int nm, double* out, hipStream_t s);
 // Backprojection out = P^T r (unpadded [N], fully overwritten) with r = resid
 // (when resid != null) else scale * (p - a y - b); x-fastest geometry.
 hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeom& rg,
                               const void* resid, const void* p, const void* y, double a, double b,
                               double scale, void* out, hipStream_t s);
-// Gradient contraction: partials[block][k] = sum_v g[v] (df/dx)[v] . u_k[v].
+// Gradient contraction: partials[k * blocks + block] = sum_v g[v] (df/dx)[v] . u_k[v].
 int contract_blocks(const pcr_grid& g);
 hipError_t launch_contract(pcr_dtype compute, pcr_dtype storage, pcr_dtype f0_dtype,
                            const pcr_grid& g, int K, const void* f0, const void* mean,

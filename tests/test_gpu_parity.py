@@ -389,12 +389,10 @@ def test_clipped_rays_are_exact(zero):
     ctx.close()
 
 
-def test_slab_clipping_is_exact():
-    """Two small objects in opposite corners: their box spans almost the
-    whole grid, but per slab the nonzero voxels are tight.  Rays clipped to
-    the slabs still give the oracle's J and gradient (which marches the whole
-    support box) on both layouts, and march far fewer samples."""
-    L = _lib()
+def _two_blob_case():
+    """Two small objects in opposite corners of the grid under a smooth
+    model: their box spans almost the whole grid, per slab their nonzero
+    voxels are tight, and rays through both cross empty space between."""
     g = S.Grid((48, 40, 36), (4.0, 4.5, 5.0))
     idx = np.indices(g.shape).astype(float)          # (z, y, x)
     f0 = np.zeros(g.shape)
@@ -408,6 +406,15 @@ def test_slab_clipping_is_exact():
     U /= np.linalg.norm(U.reshape(K, -1), axis=1)[:, None, None, None, None]
     mean = np.zeros((3,) + g.shape)
     mean[2] = 1.0
+    return g, f0, mean, U
+
+
+def test_slab_clipping_is_exact():
+    """Rays clipped to the slabs (and the warp's known zeros between them)
+    still give the oracle's J and gradient (which marches the whole support
+    box) on both layouts, and march far fewer samples."""
+    L = _lib()
+    g, f0, mean, U = _two_blob_case()
     f0_t, f0r = rounded(f0, torch.float32)
     mean_t, meanr = rounded(mean, torch.float32)
     U_t, Ur = rounded(U, torch.float32)
@@ -430,15 +437,16 @@ def test_slab_clipping_is_exact():
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["blob", "two_blobs"])
 @pytest.mark.parametrize("f16", [False, True])
-def test_warp_box_leaves_no_trace(f16):
+def test_warp_box_leaves_no_trace(f16, case):
     """The warp computes only the voxels clipped rays can sample, so cells
     outside that box keep values of earlier evaluations (other w, other
     layout).  Every evaluation of a sequence that grows and shrinks the box
     and switches between the x- and y-fastest layouts equals, bit for bit,
     the same evaluation in a fresh context."""
     L = _lib()
-    g, f0, mean, U = _blob_case(False)
+    g, f0, mean, U = _blob_case(False) if case == "blob" else _two_blob_case()
     f0_t, _ = rounded(f0, torch.float32)
     mean_t, _ = rounded(mean, torch.float32)
     U_t, _ = rounded(U, torch.float32)
