@@ -163,8 +163,16 @@ pcr_status HostBuf::ensure(size_t need)
 {
     if (p && n >= need) return PCR_OK;
     if (p) HIP_TRY(hipHostFree(p));
-    p = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault));
+    p = d = nullptr;
+    n = 0;
+    HIP_TRY(hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocCoherent | hipHostMallocMapped));
+    std::memset(p, 0, need * sizeof(double));
+    hipError_t e = hipHostGetDevicePointer((void**)&d, p, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(p);
+        p = d = nullptr;
+        return fail(PCR_EDEVICE, "host staging: %s", hipGetErrorString(e));
+    }
     n = need;
     return PCR_OK;
 }
@@ -172,7 +180,7 @@ pcr_status HostBuf::ensure(size_t need)
 void HostBuf::release()
 {
     if (p) (void)hipHostFree(p);
-    p = nullptr;
+    p = d = nullptr;
     n = 0;
 }
 
@@ -313,7 +321,7 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
                                     sizeof(double),
                                 dev, s));
     PCR_TRY(sc->moments.ensure(kMaxMoments * sizeof(double), dev, s));
-    PCR_TRY(sc->host.ensure(kMaxMoments));
+    PCR_TRY(sc->host.ensure(kHostSlots));
     return PCR_OK;
 }
 
@@ -490,7 +498,11 @@ pcr_status Evaluator::enqueue_eval(const double* w)
     effective_w(*model, w, w_eff);
     const int K = model->K;
     const int kc = mode == PCR_GRAD_FUSED ? K + 1 : 1;
-    double* mom = (double*)sc->moments.p;
+    // the final sum writes the moments straight into the host staging and
+    // then publishes this evaluation's sequence number there
+    double* mom = sc->host.d;
+    unsigned long long* done = (unsigned long long*)(sc->host.d + kDoneSlot);
+    const unsigned long long seq = ++sc->seq;
     RayGeom gc = rgc, g1 = rg;
     int vbox[6];
     const int* box = nullptr;
@@ -509,7 +521,7 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         {
             PROF(MARCH, s);
             HIP_TRY(launch_march(compute, sc->Lc, kc, gc, msc, sc->volc.p, y, nullptr,
-                                 (double*)sc->partials.p, mom, s));
+                                 (double*)sc->partials.p, mom, done, seq, s));
         }
     } else {
         {
@@ -520,12 +532,30 @@ pcr_status Evaluator::enqueue_eval(const double* w)
         {
             PROF(MARCH, s);
             HIP_TRY(launch_march(compute, sc->L1, 1, g1, ms, sc->vol1.p, y, sc->p.p,
-                                 (double*)sc->partials.p, mom, s));
+                                 (double*)sc->partials.p, mom, done, seq, s));
         }
     }
-    HIP_TRY(hipMemcpyAsync(sc->host.p, mom, (n_moments(kc) + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                           s));
     return PCR_OK;
+}
+
+pcr_status Evaluator::wait_published()
+{
+    const unsigned long long* done = (const unsigned long long*)(sc->host.p + kDoneSlot);
+    const unsigned long long want = sc->seq;
+    for (unsigned long n = 1;; ++n) {
+        if (__atomic_load_n(done, __ATOMIC_ACQUIRE) == want) return PCR_OK;
+        if ((n & 4095) == 0) {
+            // now and then: has the stream failed, or finished without
+            // publishing (which would be a bug)?
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                if (__atomic_load_n(done, __ATOMIC_ACQUIRE) == want) return PCR_OK;
+                return fail(PCR_EDEVICE, "evaluation finished without publishing its moments");
+            }
+            if (q != hipErrorNotReady) return fail(PCR_EDEVICE, "evaluation: %s", hipGetErrorString(q));
+        }
+        __builtin_ia32_pause();
+    }
 }
 
 void Evaluator::collect(Moments& out) const
@@ -541,7 +571,7 @@ void Evaluator::collect(Moments& out) const
 pcr_status Evaluator::eval_sync(const double* w, Moments& out)
 {
     PCR_TRY(enqueue_eval(w));
-    HIP_TRY(hipStreamSynchronize(s));
+    PCR_TRY(wait_published());
     collect(out);
     return PCR_OK;
 }
@@ -729,7 +759,8 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     RayGeom rg = make_ray_geom(*grid, *geom);
     MarchShape ms = choose_march_shape(rg);
     PROF(MARCH, s);
-    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, s));
+    HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, nullptr, 0,
+                         s));
     return PCR_OK;
 }
 

@@ -84,12 +84,21 @@ struct DevBuf {
     void release();
 };
 
+// Pinned, coherent host memory that kernels can write directly (d: its
+// device address).
 struct HostBuf {
     double* p = nullptr;
+    double* d = nullptr;
     size_t n = 0;
     pcr_status ensure(size_t need);
     void release();
 };
+
+// Host staging of an evaluation's results: the moments and the samples
+// count, then (at kDoneSlot, as an unsigned 64-bit word) the sequence number
+// the final-sum kernel stores once they are written.
+constexpr int kDoneSlot = kMaxMoments + 2;
+constexpr int kHostSlots = kMaxMoments + 4;
 
 // Moments of one projection (see n_moments) and the quantities of section
 // 2.2 formed from them.
@@ -136,6 +145,7 @@ struct Scratch {
                                // sized once for every admitted stream)
     DevBuf volc, vol1, acc1, p, partials, moments;
     HostBuf host;
+    unsigned long long seq = 0;   // sequence number of the last evaluation
     void release();
     size_t device_bytes() const
     {
@@ -143,8 +153,6 @@ struct Scratch {
     }
 };
 
-// Evaluates projections of trial w for one (grid, model, f0, y, geometry)
-// into one Scratch on one stream.
 // Where the warped image can be nonzero.  f0 is zero outside the index box
 // [lo, hi] of its nonzero voxels, and a displacement moves values by at most
 // max|mean_a| + sum_k |w_k| max|U_k,a| along axis a, so the warped channels
@@ -185,6 +193,8 @@ void clip_geom(const Support& sp, const pcr_grid& g, int K, const double* w_eff,
 // computes only these, since no other cell is sampled.
 void warp_box(const RayGeom& g, const pcr_grid& grid, int box[6]);
 
+// Evaluates projections of trial w for one (grid, model, f0, y, geometry)
+// into one Scratch on one stream.
 struct Evaluator {
     const pcr_grid* grid;
     const pcr_model* model;   // scale already applied through effective_w
@@ -201,9 +211,14 @@ struct Evaluator {
     int M = 0, blocks = 0, blocksc = 0, mode = PCR_GRAD_FUSED;
 
     pcr_status prepare(const void* y_, const pcr_geom& G, int mode_);
-    // Enqueues warp + march + reduce + copy of the moments to host staging.
+    // Enqueues warp + march + final sum; the sum writes the moments into the
+    // host staging and then publishes the evaluation's sequence number.
     pcr_status enqueue_eval(const double* w);
-    // After the stream reached the copy: the moments of the last eval.
+    // Spins until the last evaluation's moments are published (checking the
+    // stream for errors now and then).
+    pcr_status wait_published();
+    // After the stream finished the last eval (or it was published): its
+    // moments.
     void collect(Moments& out) const;
     pcr_status eval_sync(const double* w, Moments& out);
     // Adjoint mode: dJ/dw_eff at the w of the last eval (its p is kept).

@@ -99,8 +99,14 @@ __device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double*
 // with extra >= 0 also out[nm] = the sum of slot `extra`.  One wave per
 // output: lane l adds blocks l, l + 64, ... in order (coalesced loads), then
 // a fixed shuffle tree: deterministic.
+// With done != null the sums are stored at system scope (through to memory),
+// every wave waits for its stores to complete, and after the block barrier
+// `seq` is stored into *done with a system-scope release: a host polling
+// *done in mapped memory sees the sums once it sees seq.  One release fence
+// per launch, not one per wave.
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part, int nblocks, int nm,
-                                                 int extra, double* __restrict__ out)
+                                                 int extra, double* __restrict__ out,
+                                                 unsigned long long* done, unsigned long long seq)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nout = nm + (extra >= 0 ? 1 : 0);
@@ -110,14 +116,24 @@ __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part
 #pragma unroll 8
         for (int b = lane; b < nblocks; b += 64) s += r[b];
         s = wave_sum(s);
-        if (lane == 0) out[o] = s;
+        if (lane == 0) {
+            if (done) __hip_atomic_store(&out[o], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            else out[o] = s;
+        }
+    }
+    if (done) {
+        // every wave waits for its own stores to complete (the barrier alone
+        // does not), then one system-scope release publishes seq
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(done, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
 static hipError_t run_reduce(const double* part, int nblocks, int nm, int extra, double* out,
-                             hipStream_t s)
+                             hipStream_t s, unsigned long long* done = nullptr, unsigned long long seq = 0)
 {
-    k_reduce<<<1, 1024, 0, s>>>(part, nblocks, nm, extra, out);
+    k_reduce<<<1, 1024, 0, s>>>(part, nblocks, nm, extra, out, done, seq);
     return hipGetLastError();
 }
 
@@ -1618,7 +1634,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
 template <typename R>
 static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
                           const void* padded, const void* y, void* p_out, double* partials,
-                          double* moments, hipStream_t s)
+                          double* moments, unsigned long long* done, unsigned long long seq,
+                          hipStream_t s)
 {
     int tiles_u = tiles_u_of(rg, ms);
     int blocks = march_blocks(rg, ms);
@@ -1638,14 +1655,15 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     if (moments) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s);
+        return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s, done, seq);
     }
     return hipGetLastError();
 }
 
 static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
                             const void* padded, const void* y, void* p_out, double* partials,
-                            double* moments, hipStream_t s)
+                            double* moments, unsigned long long* done, unsigned long long seq,
+                            hipStream_t s)
 {
     MarchArgs A;
     A.g = rg;
@@ -1686,17 +1704,18 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
 #undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
-    return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s);
+    return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s, done, seq);
 }
 
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, double* moments, hipStream_t s)
+                        double* partials, double* moments, unsigned long long* done,
+                        unsigned long long seq, hipStream_t s)
 {
     if (compute == PCR_F32)
-        return march_f32(L, kc, rg, ms, padded, y, p_out, partials, moments, s);
+        return march_f32(L, kc, rg, ms, padded, y, p_out, partials, moments, done, seq, s);
     if (compute == PCR_F64)
-        return march_r<double>(L, kc, rg, ms, padded, y, p_out, partials, moments, s);
+        return march_r<double>(L, kc, rg, ms, padded, y, p_out, partials, moments, done, seq, s);
     return hipErrorInvalidValue;
 }
 

@@ -121,10 +121,14 @@ hipError_t launch_unpad(pcr_dtype compute, const PadLayout& L, const void* padde
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Ray march over kc used channels of a padded image; writes p (may be null)
 // and, when moments != null, the detector moments (y required then; uses
-// `partials`, room for march_blocks x kMaxMoments doubles).
+// `partials`, room for march_blocks x kMaxMoments doubles).  With done !=
+// null the final sum then stores `seq` into *done (system scope, after the
+// moments are visible there): moments and done may point into mapped host
+// memory.
 hipError_t launch_march(pcr_dtype compute, const PadLayout& L, int kc, const RayGeom& rg,
                         const MarchShape& ms, const void* padded, const void* y, void* p_out,
-                        double* partials, double* moments, hipStream_t s);
+                        double* partials, double* moments, unsigned long long* done,
+                        unsigned long long seq, hipStream_t s);
 // Fixed-order final sum of per-block partials: out[m] for m < nm.
 // Per slice z of f0, bounds of its nonzero voxels (i, j): sl[8 z ..] =
 // {min i, max i, min j, max j, min i+j, max i+j, min i-j, max i-j}; the
