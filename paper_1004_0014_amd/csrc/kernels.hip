@@ -783,6 +783,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.vol), (short)0, A.vol_bytes, 0x00020000);
         const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs;
+        // A step is half a voxel or less, so consecutive samples of a lane
+        // often fall in the same cell: with FP32 cells (bound by the L1) the
+        // lane keeps its last 8 cells and loads only when the cell changes
+        // (lanes that reuse are masked out of the load and cost no L1
+        // bandwidth).  FP16 cells (bound by the VALU) always load: there the
+        // branch costs more than the bandwidth it saves (measured).
+        CellPair<C> p00, p10, p01, p11;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            p00.a[c] = p00.b[c] = p10.a[c] = p10.b[c] = 0.f;
+            p01.a[c] = p01.b[c] = p11.a[c] = p11.b[c] = 0.f;
+        }
+        int last = -1;
         for (int n = na; n < nb; ++n) {
             if (n < rr.n0 || n > rr.n1) continue;
             ++nsamp;
@@ -794,24 +807,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
                         az = __builtin_amdgcn_fractf(qz);
             const int voff = ix * CB + __umul24(iy, YS) + __umul24(iz, ZS);
-            CellPair<C> p00, p10, p01, p11;
-            if constexpr (H) {
-                const char* vb = (const char*)A.vol;
-                p00 = load_pair_h<C>(vb, voff);
-                p10 = load_pair_h<C>(vb, voff + YS);
-                p01 = load_pair_h<C>(vb, voff + ZS);
-                p11 = load_pair_h<C>(vb, voff + YZ);
-            } else if constexpr (BUF) {
-                p00 = load_pair<C>(rsrc, voff, 0);
-                p10 = load_pair<C>(rsrc, voff, YS);
-                p01 = load_pair<C>(rsrc, voff, ZS);
-                p11 = load_pair<C>(rsrc, voff, YZ);
-            } else {
-                const char* vb = (const char*)A.vol;
-                p00 = load_pair_g<C>(vb, voff);
-                p10 = load_pair_g<C>(vb, voff + YS);
-                p01 = load_pair_g<C>(vb, voff + ZS);
-                p11 = load_pair_g<C>(vb, voff + YZ);
+            if (H || voff != last) {
+                last = voff;
+                if constexpr (H) {
+                    const char* vb = (const char*)A.vol;
+                    p00 = load_pair_h<C>(vb, voff);
+                    p10 = load_pair_h<C>(vb, voff + YS);
+                    p01 = load_pair_h<C>(vb, voff + ZS);
+                    p11 = load_pair_h<C>(vb, voff + YZ);
+                } else if constexpr (BUF) {
+                    p00 = load_pair<C>(rsrc, voff, 0);
+                    p10 = load_pair<C>(rsrc, voff, YS);
+                    p01 = load_pair<C>(rsrc, voff, ZS);
+                    p11 = load_pair<C>(rsrc, voff, YZ);
+                } else {
+                    const char* vb = (const char*)A.vol;
+                    p00 = load_pair_g<C>(vb, voff);
+                    p10 = load_pair_g<C>(vb, voff + YS);
+                    p01 = load_pair_g<C>(vb, voff + ZS);
+                    p11 = load_pair_g<C>(vb, voff + YZ);
+                }
             }
             const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
             const float w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
