@@ -37,8 +37,6 @@ HBM_PEAK_GBS = 8000.0
 # compile flags disable): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
 # (78.6 TFLOP/s counting an FMA as two flops).
 VALU_ISSUE_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# vector L1 delivery: 64 B per clock per CU
-L1_PEAK_TBPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -243,18 +241,23 @@ def kernel_table(prof):
             for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
 
-def profiled_traffic(name):
-    """HBM bytes per launch measured with rocprofv3 counters, from the line
-    `traffic_bytes_per_launch: <n>` of profiles/<name>.md (None if absent)."""
+def profiled_value(name, key):
+    """A figure measured with rocprofv3 counters, from the line `<key>: <n>`
+    of profiles/<name>.md (None if absent)."""
     path = os.path.join(ROOT, "profiles", name + ".md")
     try:
         for line in open(path):
-            if line.startswith("traffic_bytes_per_launch:"):
+            if line.startswith(key + ":"):
                 v = line.split(":", 1)[1].strip()
                 return None if v in ("", "null", "None") else float(v)
     except OSError:
         pass
     return None
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return profiled_value(name, "traffic_bytes_per_launch")
 
 
 def roofline(W, prof, samples_per_launch, channels, cell_bytes, traffic_profile=None):
@@ -274,16 +277,19 @@ def roofline(W, prof, samples_per_launch, channels, cell_bytes, traffic_profile=
         ops = samples_per_launch * (25 + 12 * channels)
         achieved = ops / avg_s / 1e12
         peak = VALU_ISSUE_PEAK_TOPS
-        # the cache path: 8 cells per sample through the vector L1
-        l1_bytes = samples_per_launch * 8 * cell_bytes
+        # what binds it, from the counter profile of the same kernel: the
+        # vector memory path through the L1 (tag lookups per CU and clock,
+        # peak 1; texture addresser busy fraction)
+        cprof = "march_counters_256x256x100_f32"
         return {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak,
                 "unit": "TOP/s (fp32 VALU lane-instructions)", "frac": achieved / peak,
                 "traffic": profiled_traffic(traffic_profile) if traffic_profile else None,
                 "avg_us": kt[dom]["avg_us"], "samples_per_launch": samples_per_launch,
                 "algorithmic_ops_per_launch": ops,
-                "l1_bytes_per_launch": l1_bytes,
-                "l1_achieved_TBps": l1_bytes / avg_s / 1e12, "l1_peak_TBps": L1_PEAK_TBPS,
-                "l1_frac": l1_bytes / avg_s / 1e12 / L1_PEAK_TBPS,
+                "binding_path": "vector L1 (measured, profiles/%s.md)" % cprof,
+                "l1_tag_lookups_per_cu_clock": profiled_value(cprof, "l1_tag_lookups_per_cu_clock"),
+                "ta_busy_fraction": profiled_value(cprof, "ta_busy_fraction"),
+                "l1_requested_bytes_per_sample_without_reuse": 8 * cell_bytes,
                 "compulsory_hbm_bytes_per_launch": cells * cell_bytes + 4 * W.cfg["nu"] * W.cfg["nv"]}
     if dom == "warp_fused":
         # reads mean (3) and U (3K) fields and f0 once, writes the cells

@@ -50,7 +50,6 @@ struct Slot {
     hipEvent_t ev = nullptr;
     Scratch sc;
     bool pending = false;     // an evaluation is enqueued
-    double t_enq = 0;
     pcr_status err = PCR_OK;  // a failure to start, reported by the next advance()
     double mu0 = 0;           // first trial step of the solve (0: the default rule)
     StreamDev* st = nullptr;
@@ -122,8 +121,14 @@ bool HipExec::start(int slot, const sched::Request& r, int sid, const double* w0
         return false;
     }
     sl.pending = true;
-    sl.t_enq = sched::now_s();
     return true;
+}
+
+// Whether the slot's last evaluation has published its moments.
+static bool published(const Slot& sl)
+{
+    const unsigned long long* done = (const unsigned long long*)(sl.sc.host.p + kDoneSlot);
+    return __atomic_load_n(done, __ATOMIC_ACQUIRE) == sl.sc.seq;
 }
 
 int HipExec::advance(int slot, pcr_result* res)
@@ -135,13 +140,20 @@ int HipExec::advance(int slot, pcr_result* res)
         return 2;
     }
     if (!sl.pending) return 0;
-    const hipError_t q = hipEventQuery(sl.ev);
-    if (q == hipErrorNotReady) return 0;
-    sl.pending = false;
-    if (q != hipSuccess) {
-        res->status = fail(PCR_EDEVICE, "serving slot: %s", hipGetErrorString(q));
-        return 2;
+    if (!published(sl)) {
+        const hipError_t q = hipEventQuery(sl.ev);
+        if (q == hipErrorNotReady) return 0;
+        sl.pending = false;
+        if (q != hipSuccess) {
+            res->status = fail(PCR_EDEVICE, "serving slot: %s", hipGetErrorString(q));
+            return 2;
+        }
+        if (!published(sl)) {
+            res->status = fail(PCR_EDEVICE, "serving slot: evaluation finished without publishing");
+            return 2;
+        }
     }
+    sl.pending = false;
     Moments mo;
     sl.E.collect(mo);
     auto no_grad = [](const double*, double, double, double*) { return PCR_EINVAL; };
@@ -151,7 +163,6 @@ int HipExec::advance(int slot, pcr_result* res)
         if (e == PCR_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) e = PCR_EDEVICE;
         if (e == PCR_OK) {
             sl.pending = true;
-            sl.t_enq = sched::now_s();
             return 1;
         }
     }
@@ -181,13 +192,24 @@ int HipExec::advance(int slot, pcr_result* res)
     return 2;
 }
 
-// Blocks on the slot whose pending evaluation was enqueued first.
+// Spins until some pending slot has published its moments, or (checked now
+// and then) some slot's stream has finished or failed; returns at once when
+// nothing is pending.
 void HipExec::wait_any()
 {
-    Slot* oldest = nullptr;
-    for (auto& sp : slots)
-        if (sp->pending && (!oldest || sp->t_enq < oldest->t_enq)) oldest = sp.get();
-    if (oldest) (void)hipEventSynchronize(oldest->ev);
+    for (unsigned long n = 1;; ++n) {
+        bool any = false;
+        for (auto& sp : slots) {
+            if (!sp->pending) continue;
+            any = true;
+            if (published(*sp)) return;
+        }
+        if (!any) return;
+        if ((n & 1023) == 0)
+            for (auto& sp : slots)
+                if (sp->pending && hipEventQuery(sp->ev) != hipErrorNotReady) return;
+        __builtin_ia32_pause();
+    }
 }
 
 void HipExec::forget_stream(int sid)
