@@ -204,6 +204,51 @@ def test_cost_grad_across_layouts(tiny_case):
     ctx.close()
 
 
+def _smooth_model(g, K, seed):
+    """K smooth displacement fields (unit max, each along one axis) and a
+    small mean: a model of any size for the channel-count paths."""
+    rng = np.random.default_rng(seed)
+    idx = np.indices(g.shape).astype(float)          # (z, y, x)
+    U = np.zeros((K, 3) + g.shape)
+    for k in range(K):
+        fx, fy, fz = rng.uniform(0.05, 0.25, 3)
+        U[k, k % 3] = np.cos(fx * idx[2] + fy * idx[1] + fz * idx[0] + k)
+    mean = 0.3 * np.stack([np.sin(idx[2] / 9.0), np.cos(idx[1] / 7.0), np.sin(idx[0] / 5.0)])
+    return mean, U
+
+
+@pytest.mark.parametrize("K", [1, 5, 7])
+def test_cost_grad_channel_counts(K):
+    """Fused images of 2 and 8 channels (K = 1, 5, 7) on a ragged grid, on
+    both layouts: J and the gradient follow the oracle, and so does a short
+    solve."""
+    L = _lib()
+    g = S.Grid((41, 37, 29), (4.0, 4.5, 5.0))
+    f0_t, f0 = rounded(S.phantom(g, seed=4), torch.float32)
+    mean, U = _smooth_model(g, K, seed=K)
+    mean_t, mean = rounded(mean, torch.float32)
+    U_t, U = rounded(U, torch.float32)
+    dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV))
+    ctx = L.Context(g, dm, f0_t.to(DEV))
+    rng = np.random.default_rng(20 + K)
+    w_true = rng.uniform(-3.0, 3.0, K)
+    for ang in (30.0, 88.0):
+        G = S.Geom(math.radians(ang), 80, 64, 3.0, 3.0, 2.0)
+        y_np = oracle.project(g, G, oracle.warp(g, f0, oracle.compose(g, mean, U, w_true)))
+        y = torch.tensor(y_np, dtype=torch.float32, device=DEV)
+        y_np = y.double().cpu().numpy()
+        w = 0.5 * w_true
+        J, grad = ctx.cost_grad(y, G, w, 0.9, 0.01)
+        Jo, go = oracle.cost_grad(g, G, f0, mean, U, w, y_np, 0.9, 0.01)
+        assert abs(J - Jo) <= 2e-5 * Jo, (K, ang)
+        assert rel_l2(grad, go) <= 1e-4, (K, ang)
+        ws, ab, st = ctx.reconstruct(y, G, np.zeros(K), L.default_opts(max_iter=8, step0=1.0))
+        wo, abo, sto, _ = oracle.solve(g, G, f0, mean, U, y_np, np.zeros(K),
+                                       oracle.SolveOpts(max_iter=8, step0=1.0))
+        assert rel_l2(ws, wo) <= 1e-3, (K, ang, ws, wo)
+    ctx.close()
+
+
 def test_cost_grad_fp64_compute(tiny_case):
     L = _lib()
     c = tiny_case
