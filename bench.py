@@ -339,7 +339,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--grad-mode", default="fused", choices=["fused", "adjoint"])
-    ap.add_argument("--variants", default="bf16,f16,f16-image,bf16-image,adjoint,chain,predict,fluoro,fluoro-predict",
+    ap.add_argument("--variants", default="quadratic-step,bf16,f16,f16-image,bf16-image,adjoint,chain,predict,fluoro,fluoro-predict",
                     help="extra timed runs reported beside the main line (comma list; '' = none)")
     ap.add_argument("--variant-steps", type=int, default=0,
                     help="steps of each variant (0: as many as the main run; the adjoint "
@@ -382,7 +382,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %dx%dx%d volume (%s mm), K=%d, %d projections at 1 deg steps, "
                                "%dx%d detector at %.3f mm, warm-started, <= %d iterations, "
-                               "FP32 storage, %s gradient" % (
+                               "FP32 storage, %s gradient, Armijo line search with secant first "
+                               "trials" % (
                                    args.config, *W.grid.n, "x".join("%g" % s for s in W.grid.spacing),
                                    K, Ks, W.cfg["nu"], W.cfg["nv"], W.cfg["du"], W.cfg["max_iter"],
                                    args.grad_mode),
@@ -419,11 +420,13 @@ def main():
             wv = run_sequence(ctx, W, ys[:Wm], geoms[:Wm], idxs[:Wm], o2, [0.0] * K)
             rv = run_sequence(ctx, W, ys[Wm:Wm + vsteps], geoms[Wm:Wm + vsteps],
                               idxs[Wm:Wm + vsteps], o2, wv["w"], profile=True)
-        elif v in ("predict", "fluoro", "fluoro-predict", "chain", "predict-chain"):
+        elif v in ("predict", "fluoro", "fluoro-predict", "chain", "predict-chain", "quadratic-step"):
             po = args.predict_order if "predict" in v else 0
             chain = v.endswith("chain")
             vo = _lib.default_opts(max_iter=W.cfg["max_iter"], step0=W.model.step0, grad_mode=mode,
                                    localize=1, p_ref_mm=W.p_ref)
+            if v == "quadratic-step":
+                vo.step_rule = _lib.PCR_STEP_QUADRATIC
             if v.startswith("fluoro"):
                 if fl is None:
                     fl = W.measurements(idxs[:Wm + vsteps], fixed_angle=math.radians(args.fluoro_angle))
@@ -446,6 +449,8 @@ def main():
             sv["predict_order"] = po
         if v.endswith("chain"):
             sv["step_size_carried"] = True
+        if v == "quadratic-step":
+            sv["step_rule"] = "quadratic model"
         sv["steps"] = vsteps
         sv["kernels"] = kernel_table(rv["prof"])
         variants[v] = sv

@@ -116,9 +116,7 @@ typedef struct pcr_solve_opts {
     double beta;             /* step shrink per rejected trial (0.5) */
     double eps_g;            /* stop when |g_n| <= eps_g |g_0| (1e-4) */
     double step0;            /* first trial of a solve moves w by this distance (> 0);
-                                a later iteration's first trial is the minimiser of the
-                                quadratic through the previous line's J, slope -|g|^2 and
-                                accepted J', clamped to [beta, 1/beta] x the accepted step */
+                                a later iteration's first trial: see step_rule */
     double fixed_mu;         /* > 0: constant step mu, no line search (default 0) */
     int32_t grad_mode;       /* PCR_GRAD_FUSED (default) or PCR_GRAD_ADJOINT */
     int32_t localize;        /* nonzero: localise the tumour after the solve */
@@ -129,7 +127,18 @@ typedef struct pcr_solve_opts {
                                 step0 / |g_0| -- e.g. the `mu` a previous frame's solve
                                 returned, which carries the line search's scale across
                                 warm-started frames (default 0) */
+    int32_t step_rule;       /* first trial of each later iteration (Armijo's rule,
+                                section 2.2, leaves it open): PCR_STEP_SECANT (default)
+                                s.y / y.y, with s the last accepted step in w and y the
+                                change of the gradient over it; PCR_STEP_QUADRATIC (or
+                                the secant rule when s.y <= 0): the minimiser of the
+                                quadratic through the previous line's J, slope -|g|^2
+                                and accepted J', clamped to [beta, 1/beta] x the
+                                accepted step */
 } pcr_solve_opts;
+
+#define PCR_STEP_SECANT 0
+#define PCR_STEP_QUADRATIC 1
 
 typedef struct pcr_solve_stats {
     int32_t status;          /* same as the return value */

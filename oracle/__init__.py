@@ -48,7 +48,7 @@ class _Geom(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("max_backtracks", C.c_int), ("sigma", C.c_double),
                 ("beta", C.c_double), ("eps_g", C.c_double), ("step0", C.c_double),
-                ("fixed_mu", C.c_double), ("mu0", C.c_double)]
+                ("fixed_mu", C.c_double), ("mu0", C.c_double), ("step_rule", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -252,6 +252,7 @@ class SolveOpts:
     step0: float = 1.0
     fixed_mu: float = 0.0
     mu0: float = 0.0
+    step_rule: int = 0        # later first trials: 0 secant, 1 quadratic model
 
 
 def solve(grid, geom, f0, mean, U, y, w0, opts: SolveOpts):
@@ -264,7 +265,7 @@ def solve(grid, geom, f0, mean, U, y, w0, opts: SolveOpts):
     w = np.array(w0, dtype=np.float64, copy=True)
     ab = np.zeros(2)
     o = _Opts(opts.max_iter, opts.max_backtracks, opts.sigma, opts.beta, opts.eps_g,
-              opts.step0, opts.fixed_mu, opts.mu0)
+              opts.step0, opts.fixed_mu, opts.mu0, opts.step_rule)
     st = _Stats()
     Jh = np.full(opts.max_iter + 1, np.nan)
     _load().orc_solve(C.byref(_grid(grid)), C.byref(_geom(geom)), _p(f0), K, _p(mean), _p(U),

@@ -446,12 +446,14 @@ static double next_initial_step(double J, double g2, double Jt, double mu_acc, d
  * when J' <= J - sigma mu |g|^2 (ties accept), otherwise mu <- beta mu for at
  * most max_backtracks trials; the first trial of a solve moves w by step0
  * (or uses the given step size mu0, e.g. carried over from the previous
- * frame's solve);
- * each later iteration's first trial is the minimiser of the quadratic in mu
- * that matches the previous iteration's line (its J, its slope -|g|^2 and the
- * accepted trial's J'), kept within [beta mu', mu'/beta] of the accepted mu'
- * (mu'/beta where that quadratic has no minimum); step 2 then refits (a, b)
- * at the accepted w.  Stop when |g_n| <= eps_g |g_0|, or
+ * frame's solve); step 2 then refits (a, b) at the accepted w.
+ * Each later iteration's first trial (step_rule 0, the default) is the
+ * secant step s.y / y.y, with s the last accepted step in w and y the
+ * change of the gradient over it (each gradient taken with its own a, b);
+ * where s.y <= 0, or with step_rule 1, it is the minimiser of the quadratic
+ * in mu that matches the previous iteration's line (its J, its slope -|g|^2
+ * and the accepted trial's J'), kept within [beta mu', mu'/beta] of the
+ * accepted mu' (mu'/beta where that quadratic has no minimum).  Stop when |g_n| <= eps_g |g_0|, or
  * at the iteration cap, or when the line search is exhausted (the last
  * accepted w is kept).  J_hist, if given, receives J after each step 2. */
 int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
@@ -462,6 +464,8 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
     double* p = (double*)malloc(sizeof(double) * M);
     double* grad = (double*)malloc(sizeof(double) * K);
     double* wt = (double*)malloc(sizeof(double) * K);
+    double* w_prev = (double*)malloc(sizeof(double) * K);
+    double* g_prev = (double*)malloc(sizeof(double) * K);
     double S[5];
     int status = ORC_OK, iters = 0, trials = 0;
 
@@ -495,14 +499,29 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
         }
         if (!accepted) { status = ORC_ENOCONV; break; }
         double J_line = J, g2_line = gn * gn;
-        for (int k = 0; k < K; ++k) w[k] = wt[k];
+        for (int k = 0; k < K; ++k) {
+            w_prev[k] = w[k];
+            g_prev[k] = grad[k];
+            w[k] = wt[k];
+        }
         orc_regression_sums(M, y, p, S);
         orc_step2(S, ab);
         J = orc_cost_grad(g, G, f0, K, mean, U, w, y, ab[0], ab[1], grad, NULL);
         gn = norm(K, grad);
         iters = n + 1;
         if (J_hist) J_hist[iters] = J;
-        if (!(o->fixed_mu > 0)) mu = next_initial_step(J_line, g2_line, Jt, mu, o->beta);
+        if (!(o->fixed_mu > 0)) {
+            double sy = 0.0, yy = 0.0;
+            for (int k = 0; k < K; ++k) {
+                double sk = w[k] - w_prev[k], yk = grad[k] - g_prev[k];
+                sy += sk * yk;
+                yy += yk * yk;
+            }
+            if (o->step_rule == 0 && sy > 0.0 && yy > 0.0)
+                mu = sy / yy;
+            else
+                mu = next_initial_step(J_line, g2_line, Jt, mu, o->beta);
+        }
     }
     if (st) {
         st->iterations = iters; st->trials = trials; st->status = status;
@@ -510,7 +529,7 @@ int orc_solve(const orc_grid* g, const orc_geom* G, const double* f0, int K,
         st->a = ab[0]; st->b = ab[1];
         st->mu = mu;
     }
-    free(p); free(grad); free(wt);
+    free(p); free(grad); free(wt); free(w_prev); free(g_prev);
     return status;
 }
 

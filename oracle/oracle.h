@@ -48,6 +48,8 @@ typedef struct {
     double step0;         /* first trial moves w by this distance */
     double fixed_mu;      /* > 0: constant step, no line search */
     double mu0;           /* > 0: step size of the first trial (else step0 / |g_0|) */
+    int step_rule;        /* first trial of each later iteration: 0 = secant
+                             s.y / y.y of the last step, 1 = quadratic model */
 } orc_opts;
 
 typedef struct {

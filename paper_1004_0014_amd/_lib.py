@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpcr.so")
 
 PCR_OK, PCR_EINVAL, PCR_ENOMEM, PCR_EDEVICE, PCR_ENOCONV, PCR_EDIVERGE, PCR_EBUSY = 0, -1, -2, -3, -4, -5, -6
 PCR_F32, PCR_F64, PCR_BF16, PCR_F16 = 0, 1, 2, 3
+PCR_STEP_SECANT, PCR_STEP_QUADRATIC = 0, 1
 GRAD_FUSED, GRAD_ADJOINT = 0, 1
 
 _DT = {torch.float32: PCR_F32, torch.float64: PCR_F64, torch.bfloat16: PCR_BF16,
@@ -49,7 +50,7 @@ class SolveOpts(C.Structure):
                 ("beta", C.c_double), ("eps_g", C.c_double), ("step0", C.c_double),
                 ("fixed_mu", C.c_double), ("grad_mode", C.c_int32), ("localize", C.c_int32),
                 ("p_ref_mm", C.c_double * 3), ("fp_tol_mm", C.c_double), ("fp_max_iter", C.c_int32),
-                ("mu0", C.c_double)]
+                ("mu0", C.c_double), ("step_rule", C.c_int32)]
 
 
 class SolveStats(C.Structure):

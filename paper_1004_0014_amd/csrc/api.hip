@@ -128,6 +128,8 @@ pcr_status check_opts(const pcr_solve_opts* o)
         return fail(PCR_EINVAL, "step0 must be > 0");
     if (o->grad_mode != PCR_GRAD_FUSED && o->grad_mode != PCR_GRAD_ADJOINT)
         return fail(PCR_EINVAL, "unknown grad_mode %d", o->grad_mode);
+    if (o->step_rule != PCR_STEP_SECANT && o->step_rule != PCR_STEP_QUADRATIC)
+        return fail(PCR_EINVAL, "unknown step_rule %d", o->step_rule);
     if (o->localize) {
         PCR_TRY(check_finite(o->p_ref_mm, 3, "p_ref_mm"));
         if (!(o->fp_tol_mm > 0) || o->fp_max_iter < 1) return fail(PCR_EINVAL, "bad fixed-point options");
@@ -685,6 +687,7 @@ void pcr_solve_opts_default(pcr_solve_opts* o)
     o->localize = 0;
     o->fp_tol_mm = 1e-6;
     o->fp_max_iter = 200;
+    o->step_rule = PCR_STEP_SECANT;
 }
 
 pcr_status pcr_dvf_compose(const pcr_grid* grid, const pcr_model* model, const double* w_host,

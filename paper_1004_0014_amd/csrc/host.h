@@ -229,10 +229,13 @@ struct Evaluator {
 // the caller evaluates the projection at eval_w() and feeds its moments
 // until done().  The blocking solve and the serving engine drive the same
 // machine, so a solve takes identical steps alone and in a batch.
-// Armijo's rule (section 2.2) with a per-iteration first trial: the
-// minimiser of the quadratic phi(mu) = J - g2 mu + c mu^2 that passes through
-// the accepted trial phi(mu_acc) = Jt of the line just searched, kept within
-// [beta mu_acc, mu_acc / beta] (mu_acc / beta when c <= 0).
+// Armijo's rule (section 2.2) leaves each line's first trial open.  Secant
+// rule (the default): s.y / y.y, with s the last accepted step in w and y the
+// change of the gradient over it.  Quadratic rule (and the fallback where
+// s.y <= 0): the minimiser of the quadratic phi(mu) = J - g2 mu + c mu^2 that
+// passes through the accepted trial phi(mu_acc) = Jt of the line just
+// searched, kept within [beta mu_acc, mu_acc / beta] (mu_acc / beta when
+// c <= 0).
 inline double next_initial_step(double J, double g2, double Jt, double mu_acc, double beta)
 {
     const double c = (Jt - J + mu_acc * g2) / (mu_acc * mu_acc);
@@ -312,12 +315,28 @@ inline pcr_status SolveSM::feed(const Moments& mo, GradFn&& grad_fn)
     const double Jt = mo.J(a, b);
     if (fixed || Jt <= J - o.sigma * mu * gn * gn) {
         const double J_line = J, g2_line = gn * gn;
-        for (int k = 0; k < K; ++k) w[k] = wt[k];
+        double w_prev[8], g_prev[8];
+        for (int k = 0; k < K; ++k) {
+            w_prev[k] = w[k];
+            g_prev[k] = g[k];
+            w[k] = wt[k];
+        }
         mo.step2(&a, &b);
         J = mo.J(a, b);
         PCR_TRY(gradient(w));
         iters = ++n;
-        if (!fixed) mu = next_initial_step(J_line, g2_line, Jt, mu, o.beta);
+        if (!fixed) {
+            double sy = 0.0, yy = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double sk = w[k] - w_prev[k], yk = g[k] - g_prev[k];
+                sy += sk * yk;
+                yy += yk * yk;
+            }
+            if (o.step_rule == PCR_STEP_SECANT && sy > 0.0 && yy > 0.0)
+                mu = sy / yy;
+            else
+                mu = next_initial_step(J_line, g2_line, Jt, mu, o.beta);
+        }
         advance();
         return PCR_OK;
     }

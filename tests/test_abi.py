@@ -1,6 +1,7 @@
 """CPU checks of the boundary: the built HIP library loads and exports every
-function declared in include/pcr.h; the oracle and the product share no
-code and neither imports the other."""
+function declared in include/pcr.h; the binding's structs have the header's
+layout; the oracle and the product share no code and neither imports the
+other."""
 import ctypes
 import os
 import re
@@ -42,6 +43,7 @@ def test_opts_default_without_device():
         pytest.skip("libpcr.so not built")
     o = _lib.default_opts()
     assert o.max_iter == 50 and o.max_backtracks == 30 and o.sigma == 1e-4 and o.beta == 0.5
+    assert o.step_rule == _lib.PCR_STEP_SECANT
 
 
 def _imports(path):
@@ -79,3 +81,43 @@ def test_predict_w_is_polynomial_extrapolation():
     np.testing.assert_array_equal(_lib.predict_w(quad[:1], t[:1], tn, 2), quad[0])
     with pytest.raises(_lib.PCRError):
         _lib.predict_w(quad, t[::-1], tn, 1)          # times must increase
+
+
+# ctypes mirror of each boundary struct, by its C name
+_STRUCTS = {"pcr_grid": "Grid", "pcr_geom": "Geom", "pcr_model": "Model",
+            "pcr_solve_opts": "SolveOpts", "pcr_solve_stats": "SolveStats",
+            "pcr_server_opts": "ServerOpts", "pcr_result": "Result"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding passes across the boundary has the size and
+    the field offsets the C compiler gives the header's declaration."""
+    import shutil
+    import subprocess
+    from paper_1004_0014_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pcr.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(_lib, pyname)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    cc = subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                        capture_output=True, text=True)
+    assert cc.returncode == 0, cc.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(_lib, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])

@@ -187,7 +187,7 @@ def test_line_search_on_exact_quadratic_is_block_coordinate_descent():
         a, b = ab_of(w)
         ws.append((w, a, b))
     for N in (1, 2, 3, 5):
-        opts = oracle.SolveOpts(max_iter=N, step0=0.7 * mu_star * abs(g0), eps_g=0.0)
+        opts = oracle.SolveOpts(max_iter=N, step0=0.7 * mu_star * abs(g0), eps_g=0.0, step_rule=1)
         w, (a, b), st, _ = oracle.solve(g, geom, f0, mean, U, y, [0.0], opts)
         assert st["iterations"] == N and st["trials"] == N
         np.testing.assert_allclose([w[0], a, b], ws[N - 1], rtol=1e-7, atol=1e-12)
@@ -195,7 +195,7 @@ def test_line_search_on_exact_quadratic_is_block_coordinate_descent():
     # a given first step size: mu0 = mu* makes every step the exact line
     # minimiser, and the solver reports mu* as its next step size
     for N in (1, 3):
-        opts = oracle.SolveOpts(max_iter=N, step0=1.0, eps_g=0.0, mu0=mu_star)
+        opts = oracle.SolveOpts(max_iter=N, step0=1.0, eps_g=0.0, mu0=mu_star, step_rule=1)
         wo, (ao, bo), st, _ = oracle.solve(g, geom, f0, mean, U, y, [0.0], opts)
         wm, am, bm = 0.0, *ab_of(0.0)
         for n in range(N):
@@ -205,6 +205,77 @@ def test_line_search_on_exact_quadratic_is_block_coordinate_descent():
         assert st["trials"] == N
         np.testing.assert_allclose([wo[0], ao, bo], [wm, am, bm], rtol=1e-7, atol=1e-12)
         assert abs(st["mu"] - mu_star) <= 1e-6 * mu_star
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_solver_steps_on_exact_quadratic_two_modes(rule):
+    """The same exact quadratic with two modes (both z displacements that
+    vanish near the faces, of a z-linear image): P f = p0 + w_0 q_0 + w_1 q_1
+    exactly.  A loop written here from the algorithm's statement (Armijo's
+    sufficient decrease with backtracking by beta, step 2 by least squares,
+    the first trial of a later line from the secant s.y / y.y or, for rule 1
+    or s.y <= 0, from the quadratic through the last line) on that affine map
+    alone reproduces the oracle's iterates, trial counts and next step."""
+    g = S.Grid((20, 18, 22), (5.0, 5.0, 5.0))
+    nz, ny, nx = g.shape
+    k = np.arange(nz)[:, None, None] * np.ones((nz, ny, nx))
+    f0 = 0.01 + 0.002 * k
+    bump = lambda n, e: np.where((np.arange(n) >= 3) & (np.arange(n) <= n - 4),
+                                 np.sin(np.pi * (np.arange(n) - 3) / (n - 7)) ** e, 0.0)
+    U = np.zeros((2, 3) + g.shape)
+    U[0, 2] = 4.0 * bump(nz, 2)[:, None, None] * bump(ny, 2)[None, :, None] * bump(nx, 2)[None, None, :]
+    U[1, 2] = 3.0 * bump(nz, 4)[:, None, None] * bump(ny, 2)[None, :, None] * bump(nx, 6)[None, None, :]
+    mean = np.zeros((3,) + g.shape)
+    geom = S.Geom(0.4, nu=40, nv=36, du=4.0, dv=4.0, step=2.5)
+    proj = lambda w: oracle.project(g, geom, oracle.warp(g, f0, oracle.compose(g, mean, U, w)))
+    p0 = proj([0.0, 0.0])
+    q = [proj([1.0, 0.0]) - p0, proj([0.0, 1.0]) - p0]
+    y = (proj([0.37, -0.21]) - 0.002) / 1.7
+    Y = np.stack([y.ravel(), np.ones(y.size)], axis=1)
+    pw = lambda w: p0 + w[0] * q[0] + w[1] * q[1]
+    ab_of = lambda w: np.linalg.lstsq(Y, pw(w).ravel(), rcond=None)[0]
+    Jf = lambda w, a, b: float(np.sum((pw(w) - a * y - b) ** 2))
+    gf = lambda w, a, b: np.array([2.0 * float(np.sum(qk * (pw(w) - a * y - b))) for qk in q])
+    sigma, beta, step0 = 1e-4, 0.5, 0.05
+
+    def model(N):
+        w = np.zeros(2)
+        a, b = ab_of(w)
+        J, gr = Jf(w, a, b), gf(w, a, b)
+        mu = step0 / np.linalg.norm(gr)
+        trials = 0
+        for _ in range(N):
+            while True:
+                wt = w - mu * gr
+                Jt = Jf(wt, a, b)
+                trials += 1
+                if Jt <= J - sigma * mu * float(gr @ gr):
+                    break
+                mu *= beta
+            J_line, g2 = J, float(gr @ gr)
+            s, g_old = wt - w, gr
+            w = wt
+            a, b = ab_of(w)
+            J, gr = Jf(w, a, b), gf(w, a, b)
+            yv = gr - g_old
+            if rule == 0 and s @ yv > 0 and yv @ yv > 0:
+                mu = float(s @ yv) / float(yv @ yv)
+            else:
+                c = (Jt - J_line + mu * g2) / mu ** 2
+                m = g2 / (2 * c) if c > 0 else mu / beta
+                mu = min(max(m, beta * mu), mu / beta)
+        return w, a, b, trials, mu
+
+    for N in (1, 2, 3, 5, 8):
+        wm, am, bm, tm, mum = model(N)
+        opts = oracle.SolveOpts(max_iter=N, step0=step0, eps_g=0.0, step_rule=rule)
+        wo, (ao, bo), st, _ = oracle.solve(g, geom, f0, mean, U, y, [0.0, 0.0], opts)
+        assert st["iterations"] == N and st["trials"] == tm, (N, st, tm)
+        np.testing.assert_allclose([*wo, ao, bo], [*wm, am, bm], rtol=1e-7, atol=1e-12)
+        # the next step from a secant divides by a change of the gradient:
+        # compared while the gradient is well above its rounding floor
+        if np.linalg.norm(gf(wm, am, bm)) > 1e-4 * np.linalg.norm(gf(np.zeros(2), *ab_of(np.zeros(2)))):
+            assert abs(st["mu"] - mum) <= 1e-6 * abs(mum)
 
 
 def test_localize_constant_dvf():
