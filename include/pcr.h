@@ -312,7 +312,11 @@ typedef struct pcr_server_opts {
                                  result; 1, 2 = pcr_predict_w over the stream's last
                                  results at their submit times */
     int32_t chain_step;       /* nonzero: each solve's first trial uses the step size
-                                 the stream's previous solve ended with (opts.mu0) */
+                                 the stream's previous solve ended with (opts.mu0).
+                                 Not with predict_order > 0: a carried step taken
+                                 from an extrapolated start can carry w into the
+                                 cost's degenerate minimum (the object moved out of
+                                 view, P f = 0, a = b = 0, J = 0) */
     int32_t image_f16;        /* nonzero: FP16 fused images (see pcr_ctx_set_image_dtype) */
 } pcr_server_opts;
 
