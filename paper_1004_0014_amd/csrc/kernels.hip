@@ -1575,6 +1575,7 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
                    (CellOf<R, C, H>*)padded))
 #define PCR_WF(C, T) (L.half ? PCR_WF2(C, T, true) : PCR_WF2(C, T, false))
     if (L.half && !std::is_same<R, float>::value) return hipErrorInvalidValue;
+    if (K < 1 || K > 8 || (tangent && K > L.C - 1)) return hipErrorInvalidValue;
     if (!tangent) {
         switch (L.C) {
         case 1: PCR_WF(1, false); break;
