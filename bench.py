@@ -332,6 +332,42 @@ def cpu_baseline(W, idx, iters_cap, mean_gpu_iters):
 
 
 # ---------------------------------------------------------------- main -----
+def pca_measure(W, dev, reps=5):
+    """PCA training of the motion model (section 2.1) at the workload's size:
+    the 9 training DVFs of phases 2 pi j / 10 (j = 1..9) as FP32 [9][3][N] on
+    the device, K leading components.  Reports the wall time of the training
+    call (it returns host values, so it ends synchronised), the HIP-event
+    times of its two streaming passes against HBM peak on their algorithmic
+    bytes, and the singular values against the exact ones of the model."""
+    import torch
+    from paper_1004_0014_amd import synth as S, _lib
+    g, K, R, J = W.grid, W.K, W.model.R, 9
+    d = torch.from_numpy(S.training_dvfs(g, R, n_phases=J + 1)).to(dev)
+    torch.cuda.synchronize()
+    _lib.pca_train(g, d, K)
+    walls = []
+    _lib.profile_enable(True)
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, _, sing, _ = _lib.pca_train(g, d, K)
+        walls.append(time.perf_counter() - t0)
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    E = 3 * g.N
+    algo = {"pca_gram": J * E * 4, "pca_fields": J * E * 4 + (K + 1) * E * 4}
+    kern = {}
+    for name, nbytes in algo.items():
+        if name in prof:
+            us = 1e3 * prof[name][0] / prof[name][1]
+            kern[name] = {"avg_us": us, "algorithmic_bytes": nbytes,
+                          "GB_per_s": nbytes / us * 1e-3, "frac_hbm": nbytes / us * 1e-3 / 8000.0}
+    exact = np.asarray(W.model.sing[:K], float)
+    del d
+    return {"J": J, "K": K, "reps": reps, "ms_median": 1e3 * float(np.median(walls)),
+            "kernels": kern,
+            "sing_max_rel_err": float(np.max(np.abs(np.asarray(sing) - exact) / exact))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +386,7 @@ def main():
                     help="gantry angle (deg) of the fixed-angle variants")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pca", action="store_true", help="skip the PCA-training measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the per-projection solve is a one-GPU workload "
@@ -459,6 +496,9 @@ def main():
     if variants:
         line["variants"] = variants
     ctx.close()
+    if not args.no_pca:
+        line["pca_train"] = pca_measure(W, dev)
+        log("[bench] pca_train: " + json.dumps(line["pca_train"]))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, idxs[Wm], args.cpu_iters,
                                             float(res["iters"].mean()))

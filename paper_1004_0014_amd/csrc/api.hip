@@ -203,7 +203,7 @@ void Scratch::release()
 namespace prof {
 static const char* kNames[NKERN] = {"warp_fused", "march", "reduce", "backproject", "contract",
                                     "localize", "zero", "pad", "unpad", "compose", "warp",
-                                    "warp_adjoint"};
+                                    "warp_adjoint", "pca_gram", "pca_fields"};
 struct Rec {
     hipEvent_t a, b;
     int id;

@@ -36,7 +36,7 @@ pcr_status fail(pcr_status code, const char* fmt, ...);
 // ----------------------------------------------------------- profiler ----
 namespace prof {
 enum Id { WARP, MARCH, REDUCE, BACKPROJ, CONTRACT, LOCALIZE, ZERO, PAD, UNPAD, COMPOSE, WARP_PLAIN,
-          WARP_ADJ, NKERN };
+          WARP_ADJ, PCA_GRAM, PCA_FIELDS, NKERN };
 // Brackets one launch with HIP events on `s` while profiling is enabled.
 struct Scope {
     hipStream_t s;

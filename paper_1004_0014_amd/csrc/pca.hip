@@ -57,14 +57,18 @@ __global__ void __launch_bounds__(256) k_gram(const float* __restrict__ d, size_
         partials[(size_t)blockIdx.x * P + p] = red[0][p] + red[1][p] + red[2][p] + red[3][p];
 }
 
-__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ part, int nb,
-                                                      int P, double* __restrict__ out)
+// G[p] = sum over blocks of partials[b][p]: one wave per entry, each lane
+// summing every 64th block in order, then a fixed-shape wave sum
+// (deterministic).
+__global__ void __launch_bounds__(1024) k_sum_partials(const double* __restrict__ part, int nb,
+                                                       int P, double* __restrict__ out)
 {
-    // one thread per entry, blocks summed in order (fixed order, deterministic)
-    for (int p = threadIdx.x; p < P; p += 256) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int p = wv; p < P; p += 16) {
         double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[(size_t)b * P + p];
-        out[p] = s;
+        for (int b = lane; b < nb; b += 64) s += part[(size_t)b * P + p];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) out[p] = s;
     }
 }
 
@@ -73,48 +77,62 @@ struct Coef {
     float sign[8];
 };
 
-// mean and U_k = sign_k sum_j (V_jk / sigma_k) (d_j - mean)
-__global__ void __launch_bounds__(256) k_pca_fields(const float* __restrict__ d, size_t E, int J,
-                                                    int K, Coef c, float* __restrict__ mean,
+// mean and U_k = sign_k sum_j (V_jk / sigma_k) (d_j - mean).  J is a
+// template parameter so that the J loads of an element are in flight together
+// and stay in registers.
+template <int J>
+__global__ void __launch_bounds__(256) k_pca_fields(const float* __restrict__ d, size_t E, int K,
+                                                    Coef c, float* __restrict__ mean,
                                                     float* __restrict__ U)
 {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (size_t)gridDim.x * 256) {
-        float v[kMaxJ];
+        float v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] = d[(size_t)j * E + e];
         float s = 0.f;
-        for (int j = 0; j < J; ++j) {
-            v[j] = d[(size_t)j * E + e];
-            s += v[j];
-        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) s += v[j];
         const float m = s / (float)J;
         mean[e] = m;
-        for (int k = 0; k < K; ++k) {
-            float u = 0.f;
-            for (int j = 0; j < J; ++j) u = fmaf(c.v[j * 8 + k], v[j] - m, u);
-            U[(size_t)k * E + e] = c.sign[k] * u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < K) {
+                float u = 0.f;
+#pragma unroll
+                for (int j = 0; j < J; ++j) u = fmaf(c.v[j * 8 + k], v[j] - m, u);
+                U[(size_t)k * E + e] = c.sign[k] * u;
+            }
         }
     }
 }
 
-// max |U_k| per field (bits of non-negative floats order like the floats)
+// max |U_k| per field (bits of non-negative floats order like the floats):
+// block maximum in LDS, then one atomic per block and field
 __global__ void __launch_bounds__(256) k_absmax(const float* __restrict__ U, size_t E, int K,
                                                 unsigned* __restrict__ out)
 {
+    __shared__ float red[4];
     for (int k = 0; k < K; ++k) {
         float mx = 0.f;
         for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (size_t)gridDim.x * 256)
             mx = fmaxf(mx, fabsf(U[(size_t)k * E + e]));
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
-        if ((threadIdx.x & 63) == 0) atomicMax(out + k, __float_as_uint(mx));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(out + k, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
+        __syncthreads();
     }
 }
 
 // first index whose |U_k| reaches (1 - 1e-5) of the maximum (a tolerance
 // well above FP32 rounding, so near-ties of symmetric fields resolve alike
-// in FP32 and FP64)
+// in FP32 and FP64); block minimum in LDS, one atomic per block and field
 __global__ void __launch_bounds__(256) k_first_max(const float* __restrict__ U, size_t E, int K,
                                                    const unsigned* __restrict__ mx,
                                                    unsigned long long* __restrict__ first)
 {
+    __shared__ unsigned long long red[4];
     for (int k = 0; k < K; ++k) {
         const float thr = __uint_as_float(mx[k]) * (1.0f - 1e-5f);
         unsigned long long best = ~0ull;
@@ -127,7 +145,34 @@ __global__ void __launch_bounds__(256) k_first_max(const float* __restrict__ U, 
             unsigned long long o = __shfl_down(best, off, 64);
             best = o < best ? o : best;
         }
-        if ((threadIdx.x & 63) == 0 && best != ~0ull) atomicMin(first + k, best);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long b = red[0];
+            for (int i = 1; i < 4; ++i) b = red[i] < b ? red[i] : b;
+            if (b != ~0ull) atomicMin(first + k, b);
+        }
+        __syncthreads();
+    }
+}
+
+// clears the reduction targets of the sign rule
+__global__ void k_sign_init(unsigned* __restrict__ mx, unsigned long long* __restrict__ first)
+{
+    if (threadIdx.x < 8) {
+        mx[threadIdx.x] = 0u;
+        first[threadIdx.x] = ~0ull;
+    }
+}
+
+// val[k] = U_k at its sign-deciding index
+__global__ void k_sign_pick(const float* __restrict__ U, size_t E, int K,
+                            const unsigned long long* __restrict__ first, float* __restrict__ val)
+{
+    const int k = threadIdx.x;
+    if (k < K) {
+        const unsigned long long i = first[k];
+        val[k] = i < E ? U[(size_t)k * E + i] : 0.f;
     }
 }
 
@@ -188,6 +233,14 @@ hipError_t launch_gram(const float* d, size_t E, double* part, int nb, hipStream
     return hipGetLastError();
 }
 
+template <int J>
+hipError_t launch_fields(const float* d, size_t E, int K, const Coef& c, float* mean, float* U,
+                         unsigned nb, hipStream_t s)
+{
+    k_pca_fields<J><<<nb, 256, 0, s>>>(d, E, K, c, mean, U);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -213,15 +266,18 @@ pcr_status pcr_pca_train(const pcr_grid* grid, int32_t J, const float* dvfs_dev,
     unsigned* mx = (unsigned*)((char*)small.p + 2048);
     unsigned long long* first = (unsigned long long*)((char*)small.p + 3072);
     hipError_t e;
-    switch (J) {
+    {
+        PROF(PCA_GRAM, s);
+        switch (J) {
 #define PCR_G(n) case n: e = launch_gram<n>(dvfs_dev, E, (double*)part.p, nb, s); break;
-        PCR_G(2) PCR_G(3) PCR_G(4) PCR_G(5) PCR_G(6) PCR_G(7) PCR_G(8) PCR_G(9)
-        PCR_G(10) PCR_G(11) PCR_G(12) PCR_G(13) PCR_G(14) PCR_G(15) PCR_G(16)
+            PCR_G(2) PCR_G(3) PCR_G(4) PCR_G(5) PCR_G(6) PCR_G(7) PCR_G(8) PCR_G(9)
+            PCR_G(10) PCR_G(11) PCR_G(12) PCR_G(13) PCR_G(14) PCR_G(15) PCR_G(16)
 #undef PCR_G
-    default: e = hipErrorInvalidValue;
+        default: e = hipErrorInvalidValue;
+        }
     }
     if (e != hipSuccess) { part.release(); small.release(); HIP_TRY(e); }
-    k_sum_partials<<<1, 256, 0, s>>>((const double*)part.p, nb, P, Gd);
+    k_sum_partials<<<1, 1024, 0, s>>>((const double*)part.p, nb, P, Gd);
     std::vector<double> Gu(P);
     e = hipMemcpyAsync(Gu.data(), Gd, P * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -252,22 +308,32 @@ pcr_status pcr_pca_train(const pcr_grid* grid, int32_t J, const float* dvfs_dev,
         c.sign[k] = 1.f;
     }
     const unsigned gb = (unsigned)std::min<size_t>((E + 255) / 256, 4096);
-    k_pca_fields<<<gb, 256, 0, s>>>(dvfs_dev, E, J, K, c, mean_dev, U_dev);
+    {
+        PROF(PCA_FIELDS, s);
+        switch (J) {
+#define PCR_F(n) case n: e = launch_fields<n>(dvfs_dev, E, K, c, mean_dev, U_dev, gb, s); break;
+            PCR_F(2) PCR_F(3) PCR_F(4) PCR_F(5) PCR_F(6) PCR_F(7) PCR_F(8) PCR_F(9)
+            PCR_F(10) PCR_F(11) PCR_F(12) PCR_F(13) PCR_F(14) PCR_F(15) PCR_F(16)
+#undef PCR_F
+        default: e = hipErrorInvalidValue;
+        }
+    }
+    if (e != hipSuccess) { part.release(); small.release(); HIP_TRY(e); }
     // sign rule: the first entry within 1e-5 of the largest magnitude is positive
-    std::vector<unsigned char> zero(2048, 0), ones(8 * 8, 0xff);
-    e = hipMemcpyAsync(mx, zero.data(), 8 * sizeof(unsigned), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(first, ones.data(), 8 * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) { k_absmax<<<gb, 256, 0, s>>>(U_dev, E, K, mx); e = hipGetLastError(); }
-    if (e == hipSuccess) { k_first_max<<<gb, 256, 0, s>>>(U_dev, E, K, mx, first); e = hipGetLastError(); }
-    unsigned long long fidx[8];
-    if (e == hipSuccess) e = hipMemcpyAsync(fidx, first, K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    float* pick = (float*)((char*)small.p + 3584);
+    const unsigned gr = std::min(gb, 1024u);
+    k_sign_init<<<1, 64, 0, s>>>(mx, first);
+    e = hipGetLastError();
+    if (e == hipSuccess) { k_absmax<<<gr, 256, 0, s>>>(U_dev, E, K, mx); e = hipGetLastError(); }
+    if (e == hipSuccess) { k_first_max<<<gr, 256, 0, s>>>(U_dev, E, K, mx, first); e = hipGetLastError(); }
+    if (e == hipSuccess) { k_sign_pick<<<1, 64, 0, s>>>(U_dev, E, K, first, pick); e = hipGetLastError(); }
+    float val[8] = {0.f};
+    if (e == hipSuccess) e = hipMemcpyAsync(val, pick, K * sizeof(float), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     double sgn[8];
     for (int k = 0; k < K && e == hipSuccess; ++k) {
-        float val = 0.f;
-        e = hipMemcpy(&val, U_dev + (size_t)k * E + fidx[k], sizeof(float), hipMemcpyDeviceToHost);
-        sgn[k] = val < 0.f ? -1.0 : 1.0;
-        if (e == hipSuccess && val < 0.f) {
+        sgn[k] = val[k] < 0.f ? -1.0 : 1.0;
+        if (val[k] < 0.f) {
             k_flip<<<gb, 256, 0, s>>>(U_dev, E, k);
             e = hipGetLastError();
         }

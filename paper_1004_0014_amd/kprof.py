@@ -7,7 +7,8 @@ a known size beside it to calibrate the byte counters.
     rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python3 -m paper_1004_0014_amd.kprof
 
 Each repetition is one fused cost-and-gradient evaluation (warp + march +
-reduce) at a fixed gantry angle, or one backprojection with --what backproject.
+reduce) at a fixed gantry angle, one backprojection with --what backproject,
+or one PCA training of the motion model from its 9 training DVFs with --what pca.
 """
 from __future__ import annotations
 
@@ -27,7 +28,7 @@ def main():
     ap.add_argument("--config", default="paper")
     ap.add_argument("--angle", type=float, default=30.0)
     ap.add_argument("--reps", type=int, default=10)
-    ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward"])
+    ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward", "pca"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--image", default="f32", choices=["f32", "f16"],
                     help="element type of the fused image")
@@ -46,6 +47,8 @@ def main():
     dm = dm32 if dt == torch.float32 else _lib.DeviceModel(dm32.mean.to(dt), dm32.U.to(dt))
     f0s = f0.to(dt)
     ctx = _lib.Context(g, dm, f0s, image_dtype=torch.float16 if args.image == "f16" else torch.float32)
+    if args.what == "pca":
+        d = torch.from_numpy(S.training_dvfs(g, m.R)).to(dev)
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -54,6 +57,8 @@ def main():
             ctx.cost_grad(y, G, 0.9 * w, 1.0, 0.0, mode=0 if args.what == "fused" else 1)
         elif args.what == "backproject":
             _lib.backproject_residual(g, G, y)
+        elif args.what == "pca":
+            _lib.pca_train(g, d, K)
         else:
             _lib.forward_project(g, G, f0)
         dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written

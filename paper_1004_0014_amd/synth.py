@@ -208,6 +208,14 @@ def analytic_dvf(grid: Grid, phi: float, R: int = 3, scale: float = 1.0):
 
 
 # --------------------------------------------------------------- PCA -------
+def training_dvfs(grid: Grid, R: int, n_phases: int = 10, dtype=np.float32, patterns=None):
+    """The training DVFs of the PCA model below: x(p, phi_j) at the phases
+    phi_j = 2 pi j / n_phases, j = 1..n_phases-1, as [n_phases-1][3][nz][ny][nx]."""
+    P = dvf_patterns(grid, R) if patterns is None else patterns
+    phis = 2 * np.pi * np.arange(1, n_phases) / n_phases
+    return np.tensordot(phase_coeffs(phis, R).T, P, axes=(1, 0)).astype(dtype)
+
+
 @dataclass
 class PCAModel:
     grid: Grid

@@ -68,3 +68,14 @@ def test_oracle_pca_matches_pattern_pca():
         np.testing.assert_allclose(U, m.U, atol=1e-10)
         np.testing.assert_allclose(sing, m.sing[:K], rtol=1e-10)
         np.testing.assert_allclose(wt, m.w_train, atol=1e-8)
+
+
+def test_training_dvfs_are_the_model_phases():
+    """The stacked training DVFs are the analytic motion at the model's
+    training phases (rounded to FP32)."""
+    g = S.Grid((10, 9, 7), (6.0, 6.0, 8.0))
+    d = S.training_dvfs(g, 3)
+    assert d.dtype == np.float32 and d.shape == (9, 3) + g.shape
+    for j in range(9):
+        ref = S.analytic_dvf(g, 2 * np.pi * (j + 1) / 10, 3)
+        np.testing.assert_allclose(d[j], ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
