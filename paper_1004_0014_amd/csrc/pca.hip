@@ -107,22 +107,41 @@ __global__ void __launch_bounds__(256) k_pca_fields(const float* __restrict__ d,
 }
 
 // max |U_k| per field (bits of non-negative floats order like the floats):
-// block maximum in LDS, then one atomic per block and field
-__global__ void __launch_bounds__(256) k_absmax(const float* __restrict__ U, size_t E, int K,
+// one pass over the K fields, block maximum in LDS, then one atomic per block
+// and field
+template <int K>
+__global__ void __launch_bounds__(256) k_absmax(const float* __restrict__ U, size_t E,
                                                 unsigned* __restrict__ out)
 {
-    __shared__ float red[4];
-    for (int k = 0; k < K; ++k) {
-        float mx = 0.f;
-        for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (size_t)gridDim.x * 256)
-            mx = fmaxf(mx, fabsf(U[(size_t)k * E + e]));
-        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            atomicMax(out + k, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
-        __syncthreads();
+    __shared__ float red[4][K];
+    float mx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mx[k] = 0.f;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (size_t)gridDim.x * 256) {
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = U[(size_t)k * E + e];
+#pragma unroll
+        for (int k = 0; k < K; ++k) mx[k] = fmaxf(mx[k], fabsf(v[k]));
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float m = mx[k];
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        atomicMax(out + k, __float_as_uint(fmaxf(fmaxf(red[0][k], red[1][k]), fmaxf(red[2][k], red[3][k]))));
+    }
+}
+
+template <int K>
+hipError_t launch_absmax(const float* U, size_t E, unsigned* out, unsigned nb, hipStream_t s)
+{
+    k_absmax<K><<<nb, 256, 0, s>>>(U, E, out);
+    return hipGetLastError();
 }
 
 // first index whose |U_k| reaches (1 - 1e-5) of the maximum (a tolerance
@@ -324,7 +343,14 @@ pcr_status pcr_pca_train(const pcr_grid* grid, int32_t J, const float* dvfs_dev,
     const unsigned gr = std::min(gb, 1024u);
     k_sign_init<<<1, 64, 0, s>>>(mx, first);
     e = hipGetLastError();
-    if (e == hipSuccess) { k_absmax<<<gr, 256, 0, s>>>(U_dev, E, K, mx); e = hipGetLastError(); }
+    if (e == hipSuccess) {
+        switch (K) {
+#define PCR_A(n) case n: e = launch_absmax<n>(U_dev, E, mx, gr, s); break;
+            PCR_A(1) PCR_A(2) PCR_A(3) PCR_A(4) PCR_A(5) PCR_A(6) PCR_A(7) PCR_A(8)
+#undef PCR_A
+        default: e = hipErrorInvalidValue;
+        }
+    }
     if (e == hipSuccess) { k_first_max<<<gr, 256, 0, s>>>(U_dev, E, K, mx, first); e = hipGetLastError(); }
     if (e == hipSuccess) { k_sign_pick<<<1, 64, 0, s>>>(U_dev, E, K, first, pick); e = hipGetLastError(); }
     float val[8] = {0.f};
