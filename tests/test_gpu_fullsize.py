@@ -10,7 +10,10 @@ box of the warped image):
   error against the FP64 oracle on the unrounded inputs and the fused cost;
 * the largest serving size (512x512x160 over 480x480x320 mm, 1024x768
   detector): the projection on sampled rays, computed one by one by the
-  oracle, and the fused cost of a K = 2 model.
+  oracle, and the fused cost of a K = 2 model;
+* PCA training at paper scale (9 training DVFs of 3 x 6,553,600 FP32
+  entries, K = 3), the size the benchmark measures, against the oracle's
+  direct SVD of the same FP32 DVFs.
 """
 import math
 
@@ -170,3 +173,17 @@ def test_largest_serving_size():
     Jo, go = oracle.cost_grad(g, G, f0, mean, U, w, y.double().cpu().numpy(), 1.0, 0.0)
     assert abs(J - Jo) <= 2e-5 * Jo
     assert rel_l2(grad, go) <= 1e-4
+
+
+def test_paper_scale_pca():
+    L = _L()
+    g = S.grid_for("paper")
+    d = S.training_dvfs(g, 3)
+    print("paper-scale PCA: 9 DVFs", d.shape, flush=True)
+    mean, U, sing, wt = L.pca_train(g, torch.from_numpy(d).to(DEV), 3)
+    mo, Uo, so, wo = oracle.pca(d, 3)
+    assert rel_l2(mean.cpu().numpy(), mo) <= 1e-6
+    for k in range(3):
+        assert rel_l2(U[k].cpu().numpy(), Uo[k]) <= 2e-5, k
+    np.testing.assert_allclose(sing, so, rtol=1e-6)
+    np.testing.assert_allclose(wt, wo, rtol=1e-5, atol=1e-6 * np.abs(wo).max())
