@@ -146,33 +146,57 @@ hipError_t launch_absmax(const float* U, size_t E, unsigned* out, unsigned nb, h
 
 // first index whose |U_k| reaches (1 - 1e-5) of the maximum (a tolerance
 // well above FP32 rounding, so near-ties of symmetric fields resolve alike
-// in FP32 and FP64); block minimum in LDS, one atomic per block and field
-__global__ void __launch_bounds__(256) k_first_max(const float* __restrict__ U, size_t E, int K,
+// in FP32 and FP64): one pass over the K fields, each thread stopping once it
+// has a hit in every field; block minimum in LDS, one atomic per block and
+// field
+template <int K>
+__global__ void __launch_bounds__(256) k_first_max(const float* __restrict__ U, size_t E,
                                                    const unsigned* __restrict__ mx,
                                                    unsigned long long* __restrict__ first)
 {
-    __shared__ unsigned long long red[4];
+    __shared__ unsigned long long red[4][K];
+    float thr[K];
+    unsigned long long best[K];
+#pragma unroll
     for (int k = 0; k < K; ++k) {
-        const float thr = __uint_as_float(mx[k]) * (1.0f - 1e-5f);
-        unsigned long long best = ~0ull;
-        for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (size_t)gridDim.x * 256)
-            if (fabsf(U[(size_t)k * E + e]) >= thr) {
-                best = e;
-                break;
-            }
-        for (int off = 32; off > 0; off >>= 1) {
-            unsigned long long o = __shfl_down(best, off, 64);
-            best = o < best ? o : best;
-        }
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long b = red[0];
-            for (int i = 1; i < 4; ++i) b = red[i] < b ? red[i] : b;
-            if (b != ~0ull) atomicMin(first + k, b);
-        }
-        __syncthreads();
+        thr[k] = __uint_as_float(mx[k]) * (1.0f - 1e-5f);
+        best[k] = ~0ull;
     }
+    constexpr unsigned all = (1u << K) - 1u;
+    unsigned found = 0u;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < E && found != all;
+         e += (size_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (!(found & (1u << k)) && fabsf(U[(size_t)k * E + e]) >= thr[k]) {
+                best[k] = e;
+                found |= 1u << k;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        unsigned long long b = best[k];
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned long long o = __shfl_down(b, off, 64);
+            b = o < b ? o : b;
+        }
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        unsigned long long b = red[0][k];
+        for (int i = 1; i < 4; ++i) b = red[i][k] < b ? red[i][k] : b;
+        if (b != ~0ull) atomicMin(first + k, b);
+    }
+}
+
+template <int K>
+hipError_t launch_first_max(const float* U, size_t E, const unsigned* mx, unsigned long long* first,
+                            unsigned nb, hipStream_t s)
+{
+    k_first_max<K><<<nb, 256, 0, s>>>(U, E, mx, first);
+    return hipGetLastError();
 }
 
 // clears the reduction targets of the sign rule
@@ -351,7 +375,14 @@ pcr_status pcr_pca_train(const pcr_grid* grid, int32_t J, const float* dvfs_dev,
         default: e = hipErrorInvalidValue;
         }
     }
-    if (e == hipSuccess) { k_first_max<<<gr, 256, 0, s>>>(U_dev, E, K, mx, first); e = hipGetLastError(); }
+    if (e == hipSuccess) {
+        switch (K) {
+#define PCR_M(n) case n: e = launch_first_max<n>(U_dev, E, mx, first, gr, s); break;
+            PCR_M(1) PCR_M(2) PCR_M(3) PCR_M(4) PCR_M(5) PCR_M(6) PCR_M(7) PCR_M(8)
+#undef PCR_M
+        default: e = hipErrorInvalidValue;
+        }
+    }
     if (e == hipSuccess) { k_sign_pick<<<1, 64, 0, s>>>(U_dev, E, K, first, pick); e = hipGetLastError(); }
     float val[8] = {0.f};
     if (e == hipSuccess) e = hipMemcpyAsync(val, pick, K * sizeof(float), hipMemcpyDeviceToHost, s);
