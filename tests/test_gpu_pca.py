@@ -24,3 +24,24 @@ def test_pca_train_matches_oracle(K, n):
         assert rel_l2(U[k].cpu().numpy(), Uo[k]) <= 2e-5, k
     np.testing.assert_allclose(sing, so, rtol=1e-6)
     np.testing.assert_allclose(wt, wo, rtol=1e-5, atol=1e-6 * np.abs(wo).max())
+
+
+@pytest.mark.parametrize("J,K", [(2, 1), (16, 8), (11, 5)])
+def test_pca_train_training_set_sizes(J, K):
+    """The smallest and largest training sets the entry point takes (J = 2,
+    16) and an odd one, with K up to 8, on seeded random DVFs of a ragged
+    grid: every field, singular value and coefficient against the oracle."""
+    from paper_1004_0014_amd import _lib
+    g = S.Grid((23, 17, 9), (4.0, 4.5, 6.0))
+    rng = np.random.default_rng(100 + J)
+    raw = rng.standard_normal((J, 3) + g.shape)
+    # distinct singular values, so that the fields are unique up to sign
+    raw *= (1.0 + np.arange(J))[:, None, None, None, None] ** 1.5
+    d_t, d = rounded(raw, torch.float32)
+    mean, U, sing, wt = _lib.pca_train(g, d_t.cuda(), K)
+    mo, Uo, so, wo = oracle.pca(d, K)
+    assert rel_l2(mean.cpu().numpy(), mo) <= 1e-6
+    for k in range(K):
+        assert rel_l2(U[k].cpu().numpy(), Uo[k]) <= 1e-4, k
+    np.testing.assert_allclose(sing, so, rtol=1e-6)
+    np.testing.assert_allclose(wt, wo, rtol=1e-4, atol=1e-5 * np.abs(wo).max())
