@@ -291,7 +291,7 @@ def roofline(W, prof, samples_per_launch, channels, cell_bytes, traffic_profile=
                 "ta_busy_fraction": profiled_value(cprof, "ta_busy_fraction"),
                 "l1_requested_bytes_per_sample_without_reuse": 8 * cell_bytes,
                 # the same command's kernel trace (march + final sum per launch)
-                "rocprof_avg_us": profiled_value("bench_main_256x256x100_f32",
+                "rocprof_avg_us": profiled_value("march_bench_main_256x256x100_f32",
                                                  "rocprof_march_plus_final_sum_us"),
                 "compulsory_hbm_bytes_per_launch": cells * cell_bytes + 4 * W.cfg["nu"] * W.cfg["nv"]}
     if dom == "warp_fused":
