@@ -45,6 +45,15 @@
  *   - Inputs are validated before any launch: null pointers, non-positive
  *     sizes or spacings, impossible geometry and non-finite host scalars
  *     return PCR_EINVAL and enqueue nothing.
+ *   - Size limit of FP32 compute: the FP32 ray march addresses its zero-padded
+ *     image, (nx+3)(ny+3)(nz+3) cells of C FP32 channels, with 32-bit byte
+ *     offsets.  That image must stay below 2 GiB (with padded rows below
+ *     16 MiB and (ny+3)(nz+3), (nx+3)(nz+3) below 2^24 cells).  C = 1 for
+ *     pcr_forward_project; C = K + 1 rounded up to 2, 4 or 8 for contexts and
+ *     server streams.  A larger grid returns PCR_EINVAL from
+ *     pcr_forward_project, pcr_ctx_create, pcr_cost_grad,
+ *     pcr_reconstruct_from_projection and pcr_server_add_stream before any
+ *     launch.  FP64 compute has no such limit.
  */
 #ifndef PCR_H
 #define PCR_H

@@ -63,6 +63,19 @@ pcr_status check_grid(const pcr_grid* g)
     return PCR_OK;
 }
 
+pcr_status check_march_image(const pcr_grid& g, int C, pcr_dtype compute)
+{
+    if (compute != PCR_F32) return PCR_OK;   // the FP64 march uses 64-bit offsets
+    for (int yf = 0; yf < 2; ++yf)
+        if (!march_f32_fits(make_pad(g, C, yf != 0)))
+            return fail(PCR_EINVAL,
+                        "grid (%d, %d, %d) with %d FP32 channels per cell exceeds the march's "
+                        "32-bit addressing (padded image < 2 GiB, padded rows < 16 MiB, padded "
+                        "y x z < 2^24 cells)",
+                        g.n[0], g.n[1], g.n[2], C);
+    return PCR_OK;
+}
+
 pcr_status check_geom(const pcr_geom* G)
 {
     if (!G) return fail(PCR_EINVAL, "geometry is NULL");
@@ -273,6 +286,7 @@ static void flush_locked()
 // ------------------------------------------------------------ evaluator --
 pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
 {
+    PCR_TRY(check_march_image(*grid, mode_ == PCR_GRAD_FUSED ? channels_for(model->K + 1) : 1, compute));
     y = y_;
     mode = mode_;
     rg = make_ray_geom(*grid, G);
@@ -745,6 +759,7 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     PCR_TRY(check_geom(geom));
     PCR_TRY(check_compute(compute));
     if (!vol_dev || !proj_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    PCR_TRY(check_march_image(*grid, 1, compute));
     hipStream_t s = (hipStream_t)stream;
     int dev;
     PCR_TRY(current_device(&dev));
@@ -893,10 +908,7 @@ pcr_status pcr_ctx_create(const pcr_grid* grid, const pcr_model* model, pcr_dtyp
     PCR_TRY(check_storage(f0_dtype));
     PCR_TRY(check_compute(compute));
     if (!f0_dev) return fail(PCR_EINVAL, "f0_dev is NULL");
-    const int Cc = channels_for(model->K + 1);
-    if (compute == PCR_F32 &&
-        (double)(grid->n[0] + 3) * (grid->n[1] + 3) * (grid->n[2] + 3) * Cc * 4 >= 2147483648.0)
-        return fail(PCR_EINVAL, "padded multi-channel image exceeds 2 GiB (32-bit offsets)");
+    PCR_TRY(check_march_image(*grid, channels_for(model->K + 1), compute));
     pcr_ctx* c = new (std::nothrow) pcr_ctx();
     if (!c) return fail(PCR_ENOMEM, "host allocation failed");
     c->grid = *grid;

@@ -613,16 +613,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * q + min(x, rem) + (b >> 3);
 }
 
-typedef int v2i __attribute__((ext_vector_type(2)));
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// One padded cell pair (x and x+1) of C float channels via raw buffer loads
-// at byte offset voff (+ scalar stride soff).
+// One padded cell pair (x and x+1) of C float channels.
 template <int C>
 struct CellPair {
     float a[C], b[C];
 };
-// Same pair through plain global loads (base pointer + byte offset).
+// The pair at byte offset `off` from `base` (plain global loads).
 template <int C>
 __device__ __forceinline__ CellPair<C> load_pair_g(const char* base, int off)
 {
@@ -632,38 +628,6 @@ __device__ __forceinline__ CellPair<C> load_pair_g(const char* base, int off)
     for (int c = 0; c < C; ++c) {
         p.a[c] = a[c];
         p.b[c] = a[C + c];
-    }
-    return p;
-}
-
-template <int C>
-__device__ __forceinline__ CellPair<C> load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff)
-{
-    CellPair<C> p;
-    if constexpr (C == 1) {
-        v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-        p.a[0] = __int_as_float(v.x);
-        p.b[0] = __int_as_float(v.y);
-    } else if constexpr (C == 2) {
-        v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
-        p.a[0] = __int_as_float(v.x);
-        p.a[1] = __int_as_float(v.y);
-        p.b[0] = __int_as_float(v.z);
-        p.b[1] = __int_as_float(v.w);
-    } else {
-#pragma unroll
-        for (int h = 0; h < C / 4; ++h) {
-            v4i u = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16 * h, soff, 0);
-            v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 4 * C + 16 * h, soff, 0);
-            p.a[4 * h + 0] = __int_as_float(u.x);
-            p.a[4 * h + 1] = __int_as_float(u.y);
-            p.a[4 * h + 2] = __int_as_float(u.z);
-            p.a[4 * h + 3] = __int_as_float(u.w);
-            p.b[4 * h + 0] = __int_as_float(v.x);
-            p.b[4 * h + 1] = __int_as_float(v.y);
-            p.b[4 * h + 2] = __int_as_float(v.z);
-            p.b[4 * h + 3] = __int_as_float(v.w);
-        }
     }
     return p;
 }
@@ -704,9 +668,9 @@ struct MarchArgs {
     MarchShape ms;
     int tiles_u;
     const void* vol;       // padded image, C float channels per cell
-    unsigned vol_bytes;
     int px, py, pz;        // padded dims in memory order (cells)
-    int ys, zs;            // byte strides of the padded y and z axes
+    int ys, zs;            // byte strides of the padded y and z axes (offsets are
+                           // 32-bit: march_f32_fits bounds the image)
     float fn1[3];          // clamp bound n_a + 1 (padded index space)
     int kc;                // channels used
     const float* y;        // measured projection (moments) or null
@@ -716,10 +680,9 @@ struct MarchArgs {
     float ihs[8];          // FP16 cells: 1 / channel scale
 };
 
-template <int C, bool BUF, bool H>
+template <int C, bool H>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 8 : 1))) k_march_f32(MarchArgs A)
 {
-    static_assert(!(H && BUF), "FP16 cells use global loads");
     constexpr int CB = (H ? 2 : 4) * C;   // bytes per cell
     const RayGeom& g = A.g;
     const int rpb = 256 / A.ms.seg;
@@ -780,9 +743,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         const float q0z = (float)(g.qs[2] + ta * rr.dq[2]) + 1.f;
         const float dqx = (float)(g.dt * rr.dq[0]), dqy = (float)(g.dt * rr.dq[1]),
                     dqz = (float)(g.dt * rr.dq[2]);
-        const __amdgpu_buffer_rsrc_t rsrc =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.vol), (short)0, A.vol_bytes, 0x00020000);
-        const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs;
+        const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs, PY = A.py;
         // A step is half a voxel or less, so consecutive samples of a lane
         // often fall in the same cell: with FP32 cells (bound by the L1) the
         // lane keeps its last 8 cells and loads only when the cell changes
@@ -806,7 +767,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
             const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
                         az = __builtin_amdgcn_fractf(qz);
-            const int voff = ix * CB + __umul24(iy, YS) + __umul24(iz, ZS);
+            // (iz py + iy) < 2^24 and YS < 2^24, and every offset is below
+            // the image size < 2^31 (checked at launch), so the 24-bit
+            // products are exact
+            const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
             if (H || voff != last) {
                 last = voff;
                 if constexpr (H) {
@@ -815,11 +779,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                     p10 = load_pair_h<C>(vb, voff + YS);
                     p01 = load_pair_h<C>(vb, voff + ZS);
                     p11 = load_pair_h<C>(vb, voff + YZ);
-                } else if constexpr (BUF) {
-                    p00 = load_pair<C>(rsrc, voff, 0);
-                    p10 = load_pair<C>(rsrc, voff, YS);
-                    p01 = load_pair<C>(rsrc, voff, ZS);
-                    p11 = load_pair<C>(rsrc, voff, YZ);
                 } else {
                     const char* vb = (const char*)A.vol;
                     p00 = load_pair_g<C>(vb, voff);
@@ -1410,12 +1369,6 @@ PadLayout make_pad(const pcr_grid& g, int C, bool yfast)
 
 bool prefer_yfast(const pcr_geom& G)
 {
-    // tuning override (layout sweeps): PCR_MARCH_LAYOUT = 1 x-fastest, 2 y-fastest
-    if (const char* e = std::getenv("PCR_MARCH_LAYOUT")) {
-        const int v = std::atoi(e);
-        if (v == 1) return false;
-        if (v == 2) return true;
-    }
     // Measured on the paper-scale volume: the x-fastest layout with compact
     // ray tiles is fastest at every angle except within ~15 degrees of the y
     // axis (rays along x), where the y-fastest layout with one thread per ray
@@ -1470,19 +1423,6 @@ MarchShape choose_march_shape(const RayGeom& rg)
     // both layouts)
     ms.seg = rays >= 8L * 1024 * 64 ? 1 : (rays >= 4L * 1024 * 64 ? 2 : 4);
     ms.tile_u = 4;
-    // tuning overrides (launch-shape sweeps): PCR_MARCH_TILE_U in {4..64},
-    // PCR_MARCH_SEG in {1, 2, 4}
-    if (const char* e = std::getenv("PCR_MARCH_TILE_U")) {
-        int v = std::atoi(e);
-        if (v == 4 || v == 8 || v == 16 || v == 32 || v == 64) ms.tile_u = v;
-    }
-    if (const char* e = std::getenv("PCR_MARCH_SEG")) {
-        int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4) ms.seg = v;
-    }
-    ms.buffer_loads = false;
-    if (const char* e = std::getenv("PCR_MARCH_GLOBAL")) ms.buffer_loads = std::atoi(e) == 0;
-    if (ms.tile_u > 256 / ms.seg) ms.tile_u = 256 / ms.seg;
     return ms;
 }
 
@@ -1676,18 +1616,25 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     return hipGetLastError();
 }
 
+bool march_f32_fits(const PadLayout& L)
+{
+    const double cb = (double)L.cell_bytes(4);
+    return (double)L.px * L.py * L.pz * cb < 2147483648.0 && (double)L.py * L.pz < 16777216.0 &&
+           (double)L.px * cb < 16777216.0;
+}
+
 static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const MarchShape& ms,
                             const void* padded, const void* y, void* p_out, double* partials,
                             double* moments, unsigned long long* done, unsigned long long seq,
                             hipStream_t s)
 {
+    if (!march_f32_fits(L)) return hipErrorInvalidValue;
     MarchArgs A;
     A.g = rg;
     A.ms = ms;
     A.tiles_u = tiles_u_of(rg, ms);
     A.vol = padded;
     const int cb = (int)L.cell_bytes(4);
-    A.vol_bytes = (unsigned)(L.cells() * (size_t)cb);
     A.px = L.px;
     A.py = L.py;
     A.pz = L.pz;
@@ -1701,17 +1648,11 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.partials = moments ? partials : nullptr;
     A.moments = moments;
     int blocks = march_blocks(rg, ms);
-    const bool buf = ms.buffer_loads;
-#define PCR_MF(C)                                                                                 \
-    (L.half ? k_march_f32<C, false, true><<<blocks, 256, 0, s>>>(A)                               \
-     : buf  ? k_march_f32<C, true, false><<<blocks, 256, 0, s>>>(A)                               \
-            : k_march_f32<C, false, false><<<blocks, 256, 0, s>>>(A))
     if (L.half && L.C == 1) return hipErrorInvalidValue;
+#define PCR_MF(C)                                                                                 \
+    (L.half ? k_march_f32<C, true><<<blocks, 256, 0, s>>>(A) : k_march_f32<C, false><<<blocks, 256, 0, s>>>(A))
     switch (L.C) {
-    case 1:
-        if (buf) k_march_f32<1, true, false><<<blocks, 256, 0, s>>>(A);
-        else k_march_f32<1, false, false><<<blocks, 256, 0, s>>>(A);
-        break;
+    case 1: k_march_f32<1, false><<<blocks, 256, 0, s>>>(A); break;
     case 2: PCR_MF(2); break;
     case 4: PCR_MF(4); break;
     case 8: PCR_MF(8); break;

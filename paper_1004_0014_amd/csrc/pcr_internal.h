@@ -83,7 +83,6 @@ RayGeom make_ray_geom(const pcr_grid& g, const pcr_geom& G, bool swap_xy = false
 struct MarchShape {
     int tile_u;          // pixels along u covered by one wave (64 / tile_u rows)
     int seg;             // ray segments (threads) per ray: 1, 2 or 4
-    bool buffer_loads;   // FP32 march: raw buffer loads (else global loads)
 };
 MarchShape choose_march_shape(const RayGeom& rg);
 
@@ -97,6 +96,11 @@ inline int n_moments(int kc) { return 5 + 3 * (kc - 1); }
 constexpr int kMaxMoments = 5 + 3 * 8;
 
 int march_blocks(const RayGeom& rg, const MarchShape& ms);
+// The FP32 march addresses its image with 32-bit byte offsets formed from
+// 24-bit products: it needs the image below 2^31 bytes, (padded y) x (padded
+// z) below 2^24 and the padded row below 2^24 bytes.  launch_march returns
+// hipErrorInvalidValue for an FP32 layout that does not fit.
+bool march_f32_fits(const PadLayout& L);
 
 // All launchers enqueue on `s` and return hipGetLastError().
 // `compute` is PCR_F32 or PCR_F64 throughout.

@@ -299,8 +299,7 @@ pcr_status pcr_server_add_stream(pcr_server* S, const pcr_grid* grid, const pcr_
     if (!f0_dev) return fail(PCR_EINVAL, "f0_dev is NULL");
     if (opts->grad_mode != PCR_GRAD_FUSED) return fail(PCR_EINVAL, "serving uses the fused gradient");
     const int K = model->K;
-    if ((double)(grid->n[0] + 3) * (grid->n[1] + 3) * (grid->n[2] + 3) * channels_for(K + 1) * 4 >= 2147483648.0)
-        return fail(PCR_EINVAL, "padded multi-channel image exceeds 2 GiB (32-bit offsets)");
+    PCR_TRY(check_march_image(*grid, channels_for(K + 1), PCR_F32));
     const size_t bytes = model_bytes(*grid, K, model->storage, f0_dtype);
     const size_t scratch = slot_scratch_bytes(*grid, K);
     // reserve before allocating, so that concurrent admissions see it
