@@ -213,6 +213,25 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom,
                                pcr_dtype compute, const void* vol_dev, void* proj_dev,
                                void* stream);
 
+/* Forward projection that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and result
+ * (bitwise) as pcr_forward_project, but the zero-padded copy of the volume,
+ * (nx+3)(ny+3)(nz+3) cells of 4 (F32) or 8 (F64) bytes, lives in one fixed
+ * library-owned device array of PCR_NOALLOC_SCRATCH_BYTES per GPU instead of
+ * a per-thread allocation.  The array is part of the library's code object:
+ * each GPU the library runs on holds it until the process ends; its device
+ * address is looked up once per GPU on the first call there.  A grid whose
+ * padded copy exceeds the array returns PCR_EINVAL before any launch.  Every
+ * call on one GPU shares the array (and clears and refills it): calls that
+ * overlap on one GPU (other host threads, or streams not ordered with each
+ * other) race and give undefined projections.  Not timed by the kernel
+ * profiler (pcr_profile_enable), which records events. */
+#define PCR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pcr_status pcr_forward_project_noalloc(const pcr_grid* grid, const pcr_geom* geom,
+                                       pcr_dtype compute, const void* vol_dev, void* proj_dev,
+                                       void* stream);
+
 /* Backprojection P^T resid, the exact transpose of pcr_forward_project (the
  * P^T of the gradient formula in section 2.2; no factor 2).  resid_dev
  * [nv][nu], vol_dev [N] of dtype `compute`; vol_dev is overwritten.  A

@@ -111,6 +111,7 @@ def lib():
             "pcr_warp_volume": (C.c_int32, [G, C.c_int, _P, C.c_int, _P, _P, _P]),
             "pcr_warp_adjoint": (C.c_int32, [G, C.c_int, _P, _P, _P, _P]),
             "pcr_forward_project": (C.c_int32, [G, Gm, C.c_int, _P, _P, _P]),
+            "pcr_forward_project_noalloc": (C.c_int32, [G, Gm, C.c_int, _P, _P, _P]),
             "pcr_backproject_residual": (C.c_int32, [G, Gm, C.c_int, _P, _P, _P]),
             "pcr_ctx_create": (C.c_int32, [G, Md, C.c_int, _P, C.c_int, C.POINTER(_P)]),
             "pcr_ctx_destroy": (None, [_P]),
@@ -252,6 +253,18 @@ def forward_project(grid, geom, vol: torch.Tensor, out=None, stream=None):
         out = torch.empty((G.nv, G.nu), dtype=vol.dtype, device=vol.device)
     _check(lib().pcr_forward_project(C.byref(g), C.byref(G), _dtype(vol), _ptr(vol), _ptr(out),
                                      _stream(stream)))
+    return out
+
+
+def forward_project_noalloc(grid, geom, vol: torch.Tensor, out: torch.Tensor, stream=None):
+    """pcr_forward_project_noalloc: the caller passes the output too."""
+    g, G = make_grid(grid), make_geom(geom)
+    if tuple(out.shape) != (G.nv, G.nu) or out.dtype != vol.dtype:
+        raise ValueError("out must be [nv][nu] of the volume's dtype")
+    if vol.numel() != g.n[0] * g.n[1] * g.n[2]:
+        raise ValueError("vol must hold nx*ny*nz values")
+    _check(lib().pcr_forward_project_noalloc(C.byref(g), C.byref(G), _dtype(vol), _ptr(vol),
+                                             _ptr(out), _stream(stream)))
     return out
 
 

@@ -639,6 +639,33 @@ pcr_status current_device(int* dev)
     return PCR_OK;
 }
 
+// Device array of the allocation-free projection (pcr_forward_project_noalloc).
+// Its name is a host-side stand-in: host code uses only the device address
+// looked up per device, never the name itself.
+static __device__ __align__(256) unsigned char scratch[PCR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev_ptr[kMaxScratchDevices];
+
+// The address of `scratch` on the current device `dev`, looked up on the
+// first call there.
+pcr_status scratch_on_device(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(PCR_EDEVICE, "device %d beyond the %d devices the fixed scratch table covers", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail(PCR_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        if (!p) return fail(PCR_EDEVICE, "scratch address on device %d is null", dev);
+        scratch_dev_ptr[dev] = p;
+    }
+    *out = scratch_dev_ptr[dev];
+    return PCR_OK;
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -779,6 +806,35 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     PROF(MARCH, s);
     HIP_TRY(launch_march(compute, L, 1, rg, ms, tls.pad.p, nullptr, proj_dev, nullptr, nullptr, nullptr, 0,
                          s));
+    return PCR_OK;
+}
+
+pcr_status pcr_forward_project_noalloc(const pcr_grid* grid, const pcr_geom* geom, pcr_dtype compute,
+                                       const void* vol_dev, void* proj_dev, void* stream)
+{
+    PCR_TRY(check_grid(grid));
+    PCR_TRY(check_geom(geom));
+    PCR_TRY(check_compute(compute));
+    if (!vol_dev || !proj_dev) return fail(PCR_EINVAL, "NULL device pointer");
+    PCR_TRY(check_march_image(*grid, 1, compute));
+    PadLayout L = make_pad(*grid, 1);
+    const size_t bytes = L.cells() * dtype_size(compute);
+    if (bytes > PCR_NOALLOC_SCRATCH_BYTES)
+        return fail(PCR_EINVAL,
+                    "grid (%d, %d, %d): the padded copy needs %zu bytes, more than the %zu bytes of "
+                    "the fixed scratch array",
+                    grid->n[0], grid->n[1], grid->n[2], bytes, (size_t)PCR_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = (hipStream_t)stream;
+    int dev;
+    PCR_TRY(current_device(&dev));
+    void* pad = nullptr;
+    PCR_TRY(scratch_on_device(dev, &pad));
+    // the array keeps the previous call's contents: clear the border cells
+    HIP_TRY(launch_zero(pad, bytes, s));
+    HIP_TRY(launch_pad(compute, L, vol_dev, pad, s));
+    RayGeom rg = make_ray_geom(*grid, *geom);
+    MarchShape ms = choose_march_shape(rg);
+    HIP_TRY(launch_march(compute, L, 1, rg, ms, pad, nullptr, proj_dev, nullptr, nullptr, nullptr, 0, s));
     return PCR_OK;
 }
 

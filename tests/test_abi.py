@@ -171,3 +171,25 @@ def test_march_addressing_limit_is_rejected_before_any_launch():
     assert not (st == _lib.PCR_EINVAL and b"addressing" in L.pcr_last_error())
     if h.value:
         L.pcr_ctx_destroy(h)
+
+
+def test_noalloc_projection_refuses_oversized_grid_before_any_launch():
+    """pcr_forward_project_noalloc keeps its padded copy in a fixed array of
+    PCR_NOALLOC_SCRATCH_BYTES: a grid whose padded copy is larger returns
+    PCR_EINVAL from validation, before the library touches a device (the
+    pointers passed here are never dereferenced; this runs without a GPU)."""
+    import ctypes as C
+    from paper_1004_0014_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpcr.so not built")
+    L = _lib.lib()
+    fake = C.c_void_p(0x10000)
+    G = _fake_geom()
+    # (400+3)^3 cells x 4 B = 262 MB > 64 MiB
+    g = _fake_grid((400, 400, 400))
+    st = L.pcr_forward_project_noalloc(C.byref(g), C.byref(G), _lib.PCR_F32, fake, fake, None)
+    assert st == _lib.PCR_EINVAL and b"fixed scratch" in L.pcr_last_error()
+    # FP64 doubles the cells' size: (256+3)^2 (100+3) x 8 B = 55 MB fits, (256+3)^2 (128+3) x 8 B does not
+    g = _fake_grid((256, 256, 128))
+    st = L.pcr_forward_project_noalloc(C.byref(g), C.byref(G), _lib.PCR_F64, fake, fake, None)
+    assert st == _lib.PCR_EINVAL and b"fixed scratch" in L.pcr_last_error()
