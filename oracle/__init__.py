@@ -70,6 +70,7 @@ def _load():
         G, Gm = C.POINTER(_Grid), C.POINTER(_Geom)
         sig = {
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
             "orc_interp": (C.c_double, [_PD, C.POINTER(C.c_int), _PD]),
             "orc_interp_grad": (None, [_PD, C.POINTER(C.c_int), _PD, _PD]),
             "orc_compose": (None, [G, C.c_int, _PD, _PD, _PD, _PD]),
@@ -133,6 +134,11 @@ def _n(grid):
 # ------------------------------------------------------------ wrappers -----
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel regions."""
+    _load().orc_set_num_threads(int(n))
 
 
 def interp(F, grid, q):

@@ -29,6 +29,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Sets the thread count of the later OpenMP regions (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static long vol_size(const orc_grid* g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
 
 static double fetch(const double* F, const int n[3], long i, long j, long k)

@@ -59,6 +59,7 @@ typedef struct {
 } orc_stats;
 
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Trilinear interpolant T[F](q) at index-space point q; F = 0 outside. */
 double orc_interp(const double* F, const int n[3], const double q[3]);

@@ -58,10 +58,18 @@ def rel_err(a, b):
     return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
 
 
-def run_rotation(name="paper", every=1, nu=None, dev="cuda"):
+def run_rotation(name="paper", every=1, nu=None, dev="cuda", angles=None, measure=None):
+    """Solves the projections at gantry angles `angles` (degrees; default
+    every `every`-th degree of one rotation; projection i is taken at
+    t = i / rate) in sequence, each warm-started from the previous result,
+    and scores each against the ground truth.  measure(i, geom, w_true)
+    returns the measured projection as an FP32 device tensor (default: the
+    library projects the phantom warped by the true w).  Returns a summary and
+    one row per projection (with the solved w and the localised tumour)."""
     cfg = S.config(name)
     g = S.grid_for(name)
     K = cfg["K"]
+    rate = cfg.get("rate_hz", 11.0)
     m = S.pca_model(g, K)
     f0 = torch.tensor(S.phantom(g), dtype=torch.float32, device=dev)
     dm = _lib.DeviceModel(torch.tensor(m.mean, dtype=torch.float32, device=dev),
@@ -74,20 +82,26 @@ def run_rotation(name="paper", every=1, nu=None, dev="cuda"):
     opts = _lib.default_opts(max_iter=cfg["max_iter"], step0=m.step0, localize=1, p_ref_mm=p_ref)
     w = np.zeros(K)
     rows = []
-    for i in range(0, 360, every):
-        t = i / cfg["rate_hz"]
+    for i in (range(0, 360, every) if angles is None else angles):
+        t = i / rate
         phi = S.breathing_phase(t)
         w_true = S.truth_w(m, phi)
         G = S.Geom(math.radians(i), nu, nv, du, du, cfg["step"])
         f_true = _lib.warp_volume(g, f0, _lib.dvf_compose(g, dm, w_true))
-        y = _lib.forward_project(g, G, f_true)
+        if measure is None:
+            y = _lib.forward_project(g, G, f_true)
+        else:
+            y = measure(i, G, w_true)
+        w0 = np.array(w, dtype=float)
         w, ab, st = ctx.reconstruct(y, G, w, opts)
         f_rec = _lib.warp_volume(g, f0, _lib.dvf_compose(g, dm, w))
         pt = true_tumour(g, phi, K, 1.5, p_ref)
         rows.append(dict(angle=i, e=rel_err(f_rec, f_true), e_ref=rel_err(f0, f_true),
                          loc_mm=float(np.linalg.norm(np.array(st["tumor_mm"]) - pt)),
                          loc_xyz_mm=list(np.array(st["tumor_mm"]) - pt),
-                         iterations=st["iterations"]))
+                         iterations=st["iterations"], w0=list(w0), w=list(np.asarray(w, float)),
+                         w_true=list(w_true), tumor_mm=list(st["tumor_mm"]),
+                         tumor_true_mm=list(pt), status=st["status"]))
     ctx.close()
     e = np.array([r["e"] for r in rows])
     loc = np.array([r["loc_mm"] for r in rows])

@@ -89,3 +89,61 @@ def test_fixed_angle_predicted_start(seq):
         hist.append((t, list(w)))
         assert rel_l2(w, w_true) <= 2e-2
     ctx.close()
+
+
+def _lagrange(ts, ws, t):
+    """Value at t of the polynomial through the points (ts[i], ws[i]) (numpy,
+    Lagrange form): the history prediction of section 5, restated here."""
+    ws = np.asarray(ws, float)
+    out = np.zeros(ws.shape[1])
+    for i, ti in enumerate(ts):
+        c = 1.0
+        for j, tj in enumerate(ts):
+            if j != i:
+                c *= (t - tj) / (ti - tj)
+        out += c * ws[i]
+    return out
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_predicted_start_matches_oracle(seq, order):
+    """Section 5's history-predicted initial guess: each side runs its own
+    chain of solves over the frames, every solve starting from the
+    polynomial extrapolation (degree `order`) of that side's last results to
+    the frame's time, its first trial moving w by the distance that side's
+    previous solve moved (the carried-move rule; step0 before that).  The
+    library's chain follows the oracle's frame by frame (w within 1e-3, a
+    within 1e-3), and the library's predictor equals the
+    restatement above (iteration and trial counts are printed)."""
+    L = _L()
+    g, G, m = seq["g"], seq["G"], seq["m"]
+    ctx = _ctx(seq)
+    hist_g, hist_o = [], []
+    move_g = move_o = None
+    for t, w_true, y in seq["frames"]:
+        yd = torch.tensor(y, dtype=torch.float32, device=DEV)
+        if len(hist_g) >= 2:
+            n = min(order + 1, len(hist_g))
+            w0g = L.predict_w([h[1] for h in hist_g[-n:]], [h[0] for h in hist_g[-n:]], t, order)
+            np.testing.assert_allclose(w0g, _lagrange([h[0] for h in hist_g[-n:]],
+                                                      [h[1] for h in hist_g[-n:]], t),
+                                       rtol=1e-12, atol=1e-9)
+            w0o = _lagrange([h[0] for h in hist_o[-n:]], [h[1] for h in hist_o[-n:]], t)
+        else:
+            w0g = hist_g[-1][1] if hist_g else np.zeros(seq["K"])
+            w0o = hist_o[-1][1] if hist_o else np.zeros(seq["K"])
+        s0g = m.step0 if move_g is None else min(max(move_g, 1e-3 * m.step0), m.step0)
+        s0o = m.step0 if move_o is None else min(max(move_o, 1e-3 * m.step0), m.step0)
+        wg, ab, st = ctx.reconstruct(yd, G, list(w0g), L.default_opts(max_iter=40, step0=s0g))
+        wo, abo, sto, _ = oracle.solve(g, G, seq["f0"], seq["mean"], seq["U"], y, np.array(w0o, float),
+                                       oracle.SolveOpts(max_iter=40, step0=s0o))
+        print("t %.3f: start %.2e apart, w %.2e apart, iterations %d / %d, trials %d / %d" % (
+            t, rel_l2(w0g, w0o), rel_l2(wg, wo), st["iterations"], sto["iterations"], st["trials"],
+            sto["trials"]), flush=True)
+        assert rel_l2(wg, wo) <= 1e-3, (t, wg, wo)
+        assert abs(ab[0] - abo[0]) <= 1e-3 * abs(abo[0])
+        move_g = float(np.linalg.norm(np.array(wg) - np.array(w0g)))
+        move_o = float(np.linalg.norm(np.array(wo) - np.array(w0o)))
+        hist_g.append((t, list(wg)))
+        hist_o.append((t, list(wo)))
+    ctx.close()

@@ -110,6 +110,47 @@ def test_paper_scale_solve(paper):
     assert abs(ab[0] - abo[0]) <= 1e-4 and abs(ab[1] - abo[1]) <= 1e-4 * max(1.0, abs(abo[1]))
 
 
+@pytest.mark.parametrize("i", [100, 178])
+def test_paper_scale_full_solve(paper, i):
+    """Projection i of the rotation solved to the stopping rule (relative
+    gradient 1e-4, at most 50 iterations), warm-started from the previous
+    frame's true w, then the tumour localised, against the oracle's solve and
+    localisation with the same options.  Frame 100 is a typical solve
+    (~8 iterations in the benchmark); frame 178 is one of the slowest of the
+    rotation (~40 iterations, near the turn of the breathing cycle).  Final w
+    within 1e-3, (a, b) within 1e-4; the tumour follows the DVF, which moves
+    by at most sum_k |dw_k| max|U_k| for a change dw of w, so the positions
+    agree within 1e-3 sum_k |w_k| max|U_k| plus 1e-5 mm."""
+    L = _L()
+    c = paper
+    g = c["g"]
+    cfg = S.config("paper")
+    G = S.geom_for("paper", math.radians(i))
+    w_true = S.truth_w(c["m"], S.breathing_phase(i / cfg["rate_hz"]))
+    w_prev = S.truth_w(c["m"], S.breathing_phase((i - 1) / cfg["rate_hz"]))
+    y_np = oracle.project(g, G, oracle.warp(g, c["f0"], oracle.compose(g, c["mean"], c["U"], w_true)))
+    y_t, y_np = rounded(y_np, torch.float32)
+    p_ref = S.tumor_center(g)
+    ctx = L.Context(g, c["dm"], c["df0"])
+    w, ab, st = ctx.reconstruct(y_t.to(DEV), G, w_prev,
+                                L.default_opts(max_iter=cfg["max_iter"], step0=c["m"].step0,
+                                               localize=1, p_ref_mm=p_ref))
+    ctx.close()
+    print("frame %d: library %d iterations, %d trials, status %d" % (i, st["iterations"], st["trials"],
+                                                                     st["status"]), flush=True)
+    wo, abo, sto, _ = oracle.solve(g, G, c["f0"], c["mean"], c["U"], y_np, w_prev,
+                                   oracle.SolveOpts(max_iter=cfg["max_iter"], step0=c["m"].step0))
+    po, fst, _ = oracle.localize(g, c["mean"], c["U"], wo, p_ref)
+    print("frame %d: oracle %d iterations, %d trials, status %d; w %.2e apart, tumour %.2e mm apart" % (
+        i, sto["iterations"], sto["trials"], sto["status"], rel_l2(w, wo),
+        np.linalg.norm(np.array(st["tumor_mm"]) - po)), flush=True)
+    assert st["status"] == 0 and sto["status"] == 0
+    assert rel_l2(w, wo) <= 1e-3, (w, wo)
+    assert abs(ab[0] - abo[0]) <= 1e-4 and abs(ab[1] - abo[1]) <= 1e-4 * max(1.0, abs(abo[1]))
+    umax = np.abs(c["U"]).reshape(len(wo), -1).max(axis=1)
+    assert np.linalg.norm(np.array(st["tumor_mm"]) - po) <= 1e-3 * np.sum(np.abs(wo) * umax) + 1e-5
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_precision_scale_16bit(storage):
     L = _L()
@@ -166,11 +207,13 @@ def test_largest_serving_size():
     U_t, U = rounded(m.U, torch.float32)
     dm = L.DeviceModel(mean_t.to(DEV), U_t.to(DEV))
     w = S.truth_w(m, 2.2)
-    y = torch.tensor(p, dtype=torch.float32, device=DEV)
+    # the measurement from the oracle (the projection of the unwarped image)
+    y_t, y_np = rounded(oracle.project(g, G, f0), torch.float32)
+    y = y_t.to(DEV)
     ctx = L.Context(g, dm, df0)
     J, grad = ctx.cost_grad(y, G, w, 1.0, 0.0)
     ctx.close()
-    Jo, go = oracle.cost_grad(g, G, f0, mean, U, w, y.double().cpu().numpy(), 1.0, 0.0)
+    Jo, go = oracle.cost_grad(g, G, f0, mean, U, w, y_np, 1.0, 0.0)
     assert abs(J - Jo) <= 2e-5 * Jo
     assert rel_l2(grad, go) <= 1e-4
 
@@ -187,3 +230,41 @@ def test_paper_scale_pca():
         assert rel_l2(U[k].cpu().numpy(), Uo[k]) <= 2e-5, k
     np.testing.assert_allclose(sing, so, rtol=1e-6)
     np.testing.assert_allclose(wt, wo, rtol=1e-5, atol=1e-6 * np.abs(wo).max())
+
+
+@pytest.mark.parametrize("angle", [30.0, 85.0])
+def test_paper_scale_backprojection(angle):
+    """P^T r at paper scale (the backprojection of the paper-order gradient
+    and of the autograd gradient in f0) for a seeded residual, element by
+    element.  A voxel sums r dt w over the samples whose cell it is a corner
+    of.  FP32 sample positions carry an absolute error of up to ~6e-5 voxel
+    (q = q_s + t dq cancels terms of ~500 voxels), so each trilinear weight
+    is off by up to ~1e-4 in absolute terms, whatever its size; the 8 weights
+    of a sample sum to 1 and its corners lie in the 3x3x3 voxels around any
+    one of them, so the sum of |r| dt over the samples touching voxel v is at
+    most the 3x3x3 box sum of B = P^T |r| around v.  Hence |dg[v]| <=
+    1e-4 box27(B)[v] + 1e-5 B[v] (FP32 sums); plus the relative L2 error."""
+    L = _L()
+    g = S.grid_for("paper")
+    G = S.geom_for("paper", math.radians(angle))
+    rng = np.random.default_rng(13)
+    r_t, r = rounded(rng.standard_normal((G.nv, G.nu)), torch.float32)
+    print("backprojection at paper scale, angle", angle, flush=True)
+    b = L.backproject_residual(g, G, r_t.to(DEV)).cpu().double().numpy()
+    bo = oracle.backproject(g, G, r)
+    babs = oracle.backproject(g, G, np.abs(r))
+    err = np.abs(b - bo)
+    box = np.zeros_like(babs)
+    pad = np.pad(babs, 1)
+    nz, ny, nx = babs.shape
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                box += pad[dz:dz + nz, dy:dy + ny, dx:dx + nx]
+    bound = 1e-4 * box + 1e-5 * babs
+    ratio = float(np.max(err / (bound + 1e-300)))
+    print("max |dg| / bound = %.3e, max |dg| / P^T|r| = %.3e, rel L2 = %.3e" % (
+        ratio, float(np.max(err / (babs + 1e-300))), rel_l2(b, bo)), flush=True)
+    assert np.all(err <= bound)
+    assert rel_l2(b, bo) <= 1e-5
+    assert np.count_nonzero(babs) > 0.3 * babs.size      # the cone covers much of the volume
