@@ -346,6 +346,12 @@ typedef struct pcr_server_opts {
                                  cost's degenerate minimum (the object moved out of
                                  view, P f = 0, a = b = 0, J = 0) */
     int32_t image_f16;        /* nonzero: FP16 fused images (see pcr_ctx_set_image_dtype) */
+    int32_t carry_move;       /* nonzero: each solve's first trial moves w by the distance
+                                 the stream's previous solve moved it (from its start to
+                                 its result), kept within [1e-3, 1] x the stream's step0;
+                                 scale-free, and the first trial that suits a predicted
+                                 start (predict_order > 0), whose error is about the
+                                 previous prediction's.  Not with chain_step */
 } pcr_server_opts;
 
 typedef struct pcr_result {
@@ -362,6 +368,8 @@ typedef struct pcr_result {
                                  ended with (see pcr_solve_opts.mu0) */
     double samples;           /* ray samples marched over all projections of the
                                  solve (the work it took; see pcr_solve_stats) */
+    double step0;             /* distance the first trial was to move w (pcr_solve_opts.step0;
+                                 0 when mu0 set the first trial) */
 } pcr_result;
 
 /* Creates the server and its worker thread on the current device. */
@@ -408,6 +416,11 @@ size_t pcr_server_device_bytes(const pcr_server* srv);
  * the process; thread-safe. */
 void pcr_profile_enable(int32_t on);
 int32_t pcr_profile_read(int32_t max, const char** names, double* total_ms, int64_t* counts);
+/* Restricts that timing to the kernel kinds whose bit is set in `mask` (bit
+ * i: the i-th name pcr_profile_read reports; all bits set by default), so
+ * that timing the dominant kernel leaves the others' launches free of event
+ * records.  Global to the process; thread-safe. */
+void pcr_profile_select(uint32_t mask);
 
 #ifdef __cplusplus
 }

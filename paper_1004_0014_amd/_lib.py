@@ -68,7 +68,8 @@ class SolveStats(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("drop_stale", C.c_int32),
-                ("predict_order", C.c_int32), ("chain_step", C.c_int32), ("image_f16", C.c_int32)]
+                ("predict_order", C.c_int32), ("chain_step", C.c_int32), ("image_f16", C.c_int32),
+                ("carry_move", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -77,7 +78,8 @@ class Result(C.Structure):
                 ("fp_status", C.c_int32), ("w0", C.c_double * 8), ("w", C.c_double * 8),
                 ("ab", C.c_double * 2), ("J", C.c_double), ("tumor_mm", C.c_double * 3),
                 ("t_submit_s", C.c_double), ("t_start_s", C.c_double), ("t_done_s", C.c_double),
-                ("mu0", C.c_double), ("mu", C.c_double), ("samples", C.c_double)]
+                ("mu0", C.c_double), ("mu", C.c_double), ("samples", C.c_double),
+                ("step0", C.c_double)]
 
     def as_dict(self):
         K = self.K
@@ -86,7 +88,7 @@ class Result(C.Structure):
                 "w0": list(self.w0[:K]), "w": list(self.w[:K]), "ab": list(self.ab), "J": self.J,
                 "tumor_mm": list(self.tumor_mm), "t_submit_s": self.t_submit_s,
                 "t_start_s": self.t_start_s, "t_done_s": self.t_done_s, "mu0": self.mu0,
-                "mu": self.mu, "samples": self.samples}
+                "mu": self.mu, "samples": self.samples, "step0": self.step0}
 
 
 _lib = None
@@ -139,6 +141,7 @@ def lib():
             "pcr_predict_w": (C.c_int32, [_PD, _PD, C.c_int32, C.c_int32, C.c_double, C.c_int32, _PD]),
             "pcr_pca_train": (C.c_int32, [G, C.c_int32, _P, C.c_int32, _P, _P, _PD, _PD, _P]),
             "pcr_profile_enable": (None, [C.c_int32]),
+            "pcr_profile_select": (None, [C.c_uint32]),
             "pcr_profile_read": (C.c_int32, [C.c_int32, C.POINTER(C.c_char_p), _PD,
                                              C.POINTER(C.c_int64)]),
         }
@@ -387,8 +390,15 @@ class Context:
         return [w[k] for k in range(self.K)], (ab[0], ab[1]), st.as_dict()
 
 
-def profile_enable(on: bool = True):
-    """Per-kernel HIP-event timing inside the library (resets when enabled)."""
+PROFILE_KINDS = ("warp_fused", "march", "reduce", "backproject", "contract", "localize", "zero", "pad",
+                 "unpad", "compose", "warp", "warp_adjoint", "pca_gram", "pca_fields")
+
+
+def profile_enable(on: bool = True, kinds=None):
+    """Per-kernel HIP-event timing inside the library (resets when enabled),
+    of every kernel kind or only of `kinds` (names as profile_read reports)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << PROFILE_KINDS.index(k) for k in kinds)
+    lib().pcr_profile_select(mask)
     lib().pcr_profile_enable(1 if on else 0)
 
 
@@ -408,9 +418,10 @@ class Server:
     into server-owned device memory at add_stream."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, drop_stale: bool = True,
-                 predict_order: int = 0, chain_step: bool = False, image_f16: bool = False):
+                 predict_order: int = 0, chain_step: bool = False, image_f16: bool = False,
+                 carry_move: bool = False):
         o = ServerOpts(int(hbm_budget_bytes), int(max_slots), 1 if drop_stale else 0, int(predict_order),
-                       1 if chain_step else 0, 1 if image_f16 else 0)
+                       1 if chain_step else 0, 1 if image_f16 else 0, 1 if carry_move else 0)
         h = C.c_void_p()
         _check(lib().pcr_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -56,7 +56,7 @@ pcr_status check_grid(const pcr_grid* g)
             return fail(PCR_EINVAL, "grid spacing[%d] must be finite and > 0", a);
         if (!std::isfinite(g->origin_mm[a])) return fail(PCR_EINVAL, "grid origin must be finite");
     }
-    if (g->n[2] > 65535 || (g->n[1] + 31) / 32 > 65535)
+    if (g->n[2] > 65535 || g->n[1] > 65535)
         return fail(PCR_EINVAL, "grid n = (%d, %d, %d) exceeds the launch limits", g->n[0], g->n[1], g->n[2]);
     double cells = (double)(g->n[0] + 3) * (g->n[1] + 3) * (g->n[2] + 3);
     if (cells > 2.0e9) return fail(PCR_EINVAL, "grid too large (%.3g padded cells)", cells);
@@ -223,6 +223,7 @@ struct Rec {
 };
 static std::mutex mu;
 static bool enabled = false;
+static uint32_t mask = 0xffffffffu;
 static std::vector<Rec> pending;
 static std::vector<hipEvent_t> pool;
 static double total_ms[NKERN];
@@ -244,7 +245,7 @@ static hipEvent_t get_event()
 Scope::Scope(int id_, hipStream_t s_) : s(s_), id(id_)
 {
     std::lock_guard<std::mutex> lk(mu);
-    if (!enabled) return;
+    if (!enabled || !((mask >> id) & 1u)) return;
     a = get_event();
     if (a && hipEventRecord(a, s) != hipSuccess) {
         pool.push_back(a);
@@ -698,6 +699,12 @@ void pcr_profile_enable(int32_t on)
         prof::dropped = 0;
     }
     prof::enabled = on != 0;
+}
+
+void pcr_profile_select(uint32_t mask)
+{
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::mask = mask;
 }
 
 int32_t pcr_profile_read(int32_t max, const char** names, double* total_ms, int64_t* counts)

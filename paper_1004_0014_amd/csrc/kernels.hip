@@ -278,7 +278,9 @@ struct VoxBox {
     int lo[3], hi[3];
 };
 
-// x-fastest padded layout: block 64 (x) x 4 (y), coalesced in x both ways.
+// x-fastest padded layout: a block per 256-voxel run along x, coalesced in x
+// both ways (longer runs than 64 x 4 blocks: 49.5 against 57.7 us at paper
+// scale).
 template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
                                                     const S* __restrict__ mean,
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
                                                     Chan<float, 8> hs, VoxBox b,
                                                     CellOf<R, C, H>* __restrict__ out)
 {
-    const int i = b.lo[0] + blockIdx.x * 64 + threadIdx.x, j = b.lo[1] + blockIdx.y * 4 + threadIdx.y;
+    const int i = b.lo[0] + blockIdx.x * 256 + threadIdx.x, j = b.lo[1] + blockIdx.y;
     const int k = b.lo[2] + blockIdx.z;
     if (i >= b.hi[0] || j >= b.hi[1]) return;
     Chan<R, C> o = warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k);
@@ -295,8 +297,9 @@ __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
         store_cell<R, C, H>(o, hs);
 }
 
-// y-fastest padded layout: a 32 x 32 (x, y) tile per block, computed with
-// x-contiguous reads, staged in LDS and written as 32-cell runs along y.
+// y-fastest padded layout: a 128 x 8 (x, y) tile per block, computed with
+// x-contiguous reads (512-byte runs of each field), staged in LDS and written
+// as 8-cell runs along y.
 template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        const S* __restrict__ mean,
@@ -305,19 +308,20 @@ __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        int py, Chan<float, 8> hs, VoxBox b,
                                                        CellOf<R, C, H>* __restrict__ out)
 {
-    __shared__ CellOf<R, C, H> tile[32][33];
-    const int i0 = b.lo[0] + blockIdx.x * 32, j0 = b.lo[1] + blockIdx.y * 32, k = b.lo[2] + blockIdx.z;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    __shared__ CellOf<R, C, H> tile[8][129];
+    const int i0 = b.lo[0] + blockIdx.x * 128, j0 = b.lo[1] + blockIdx.y * 8, k = b.lo[2] + blockIdx.z;
+    const int t = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int i = i0 + tx, j = j0 + ty + 8 * r;
+        const int il = t & 127, jl = (t >> 7) + 2 * r;
+        const int i = i0 + il, j = j0 + jl;
         if (i < b.hi[0] && j < b.hi[1])
-            tile[ty + 8 * r][tx] = store_cell<R, C, H>(warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k), hs);
+            tile[jl][il] = store_cell<R, C, H>(warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k), hs);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int jl = tx, il = ty + 8 * r;
+        const int jl = t & 7, il = (t >> 3) + 32 * r;
         const int i = i0 + il, j = j0 + jl;
         if (i < b.hi[0] && j < b.hi[1])
             out[(size_t)(j + 1) + (size_t)px * ((size_t)(i + 1) + (size_t)py * (k + 1))] = tile[jl][il];
@@ -825,6 +829,304 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
     if (owner && A.p_out) A.p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
     if (A.partials) {
         // record per block: the moments, then the number of samples marched
+        constexpr int NM = 5 + 3 * (C - 1);
+        double mo[NM + 1];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) mo[i] = 0.0;
+        mo[NM] = (double)nsamp;
+        if (owner) {
+            double yd = (double)A.y[iu + (size_t)g.nu * iv];
+            double pd = (double)(dt * acc[0]);
+            mo[0] = yd;
+            mo[1] = yd * yd;
+            mo[2] = pd;
+            mo[3] = yd * pd;
+            mo[4] = pd * pd;
+#pragma unroll
+            for (int k = 0; k < C - 1; ++k) {
+                if (k + 1 < A.kc) {
+                    double tk = (double)(dt * acc[k + 1]);
+                    mo[5 + 3 * k] = pd * tk;
+                    mo[6 + 3 * k] = yd * tk;
+                    mo[7 + 3 * k] = tk;
+                }
+            }
+        }
+        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x);
+    }
+}
+
+// ------------------------------------------ FP32 ray march, LDS-staged ----
+// The same march as k_march_f32 (same rays per wave, same segments, same
+// sample positions, weights and summation order: bitwise the same sums), but
+// each wave gathers its taps from a private LDS copy of the cells it is about
+// to sample instead of through the vector L1.  The wave's sample range is cut
+// into chunks of S sample indices; for each chunk the wave finds the index
+// box of the cells its active lanes will read (the floor cells of the first
+// and last sample of each lane's share of the chunk, plus one: positions are
+// monotone in n, so the extremes bound every sample between), copies that
+// box from the image into LDS with coalesced row loads (one 16-byte lane
+// load per cell at C = 4), and marches the chunk out of LDS.  A chunk whose
+// box exceeds the wave's buffer is retried at half the length; at the
+// shortest length it falls back to gathering through the L1.  A short box
+// grows the next chunk.  Each staged cell serves ~40 sample taps at paper
+// scale, so the L1 sees a few coalesced row loads per chunk instead of 8
+// scattered cells per sample.
+constexpr int kStageBytes = 8192;     // LDS per wave
+
+// Cells `cell` and `cell` + 1 of a staging buffer of C-float cells.
+template <int C>
+__device__ __forceinline__ void lds_pair(const float* st, int cell, float (&a)[C], float (&b)[C])
+{
+    if constexpr (C % 4 == 0) {
+        const float4* q = (const float4*)(st + cell * C);
+#pragma unroll
+        for (int h = 0; h < C / 4; ++h) {
+            const float4 u = q[h], v = q[C / 4 + h];
+            a[4 * h] = u.x; a[4 * h + 1] = u.y; a[4 * h + 2] = u.z; a[4 * h + 3] = u.w;
+            b[4 * h] = v.x; b[4 * h + 1] = v.y; b[4 * h + 2] = v.z; b[4 * h + 3] = v.w;
+        }
+    } else if constexpr (C == 2) {
+        const float2 u = *(const float2*)(st + cell * 2), v = *(const float2*)(st + cell * 2 + 2);
+        a[0] = u.x; a[1] = u.y; b[0] = v.x; b[1] = v.y;
+    } else {
+        a[0] = st[cell];
+        b[0] = st[cell + 1];
+    }
+}
+
+// Copies one C-float cell (global, 4C-byte aligned) into a staging buffer.
+template <int C>
+__device__ __forceinline__ void stage_cell(const char* src, float* dst)
+{
+    if constexpr (C % 4 == 0) {
+#pragma unroll
+        for (int h = 0; h < C / 4; ++h) ((float4*)dst)[h] = ((const float4*)src)[h];
+    } else if constexpr (C == 2) {
+        *(float2*)dst = *(const float2*)src;
+    } else {
+        *dst = *(const float*)src;
+    }
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 4 : 1))) k_march_lds(MarchArgs A)
+{
+    constexpr int CB = 4 * C;                    // bytes per cell
+    constexpr int BUF = kStageBytes / CB;        // cells per wave
+    const RayGeom& g = A.g;
+    const int rpb = 256 / A.ms.seg;
+    const int rloc = threadIdx.x % rpb, sid = threadIdx.x / rpb;
+    const int rows = rpb / A.ms.tile_u;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tu = tile % A.tiles_u, tv = tile / A.tiles_u;
+    const int iu = tu * A.ms.tile_u + rloc % A.ms.tile_u;
+    const int iv = tv * rows + rloc / A.ms.tile_u;
+    const bool valid = iu < g.nu && iv < g.nv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    int nsamp = 0;
+    RayRange rr;
+    rr.n0 = 0;
+    rr.n1 = -1;
+    rr.dq[0] = rr.dq[1] = rr.dq[2] = 0.0;
+    // LDS: the block's ray set-ups, then the waves' staging buffers, then
+    // the segments' partial sums (one after the other, so they share it)
+    constexpr int kStage = 4 * kStageBytes;
+    constexpr int kRest = 256 * C * 4 > 128 * (int)sizeof(RayRange) ? 256 * C * 4 : 128 * (int)sizeof(RayRange);
+    constexpr int kSmem = kStage > kRest ? kStage : kRest;
+    __shared__ __align__(16) char smem[kSmem];
+    if (A.ms.seg > 1) {
+        RayRange* rbuf = (RayRange*)smem;
+        if (sid == 0) {
+            if (valid) rr = ray_range(g, iu, iv);
+            rbuf[rloc] = rr;
+        }
+        __syncthreads();
+        rr = rbuf[rloc];
+        __syncthreads();   // before the buffer is reused for staging
+    } else if (valid) {
+        rr = ray_range(g, iu, iv);
+    }
+    int N0 = rr.n1 >= rr.n0 ? rr.n0 : INT_MAX, N1 = rr.n1 >= rr.n0 ? rr.n1 : INT_MIN;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        N0 = min(N0, __shfl_xor(N0, o));
+        N1 = max(N1, __shfl_xor(N1, o));
+    }
+    N0 = __builtin_amdgcn_readfirstlane(N0);
+    N1 = __builtin_amdgcn_readfirstlane(N1);
+    float* st = (float*)(smem + wave * kStageBytes);
+    if (N0 <= N1) {
+        const long span = (long)N1 - N0 + 1;
+        const int na = __builtin_amdgcn_readfirstlane(N0 + (int)(span * sid / A.ms.seg));
+        const int nb = __builtin_amdgcn_readfirstlane(N0 + (int)(span * (sid + 1) / A.ms.seg));
+        const double ta = (double)na * g.dt;
+        const float q0x = (float)(g.qs[0] + ta * rr.dq[0]) + 1.f;
+        const float q0y = (float)(g.qs[1] + ta * rr.dq[1]) + 1.f;
+        const float q0z = (float)(g.qs[2] + ta * rr.dq[2]) + 1.f;
+        const float dqx = (float)(g.dt * rr.dq[0]), dqy = (float)(g.dt * rr.dq[1]),
+                    dqz = (float)(g.dt * rr.dq[2]);
+        const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs, PY = A.py;
+        const char* vb = (const char*)A.vol;
+        CellPair<C> p00, p10, p01, p11;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            p00.a[c] = p00.b[c] = p10.a[c] = p10.b[c] = 0.f;
+            p01.a[c] = p01.b[c] = p11.a[c] = p11.b[c] = 0.f;
+        }
+        int S = 16;
+        bool gather = false;   // the rest of the range through the L1
+        for (int c0 = na; c0 < nb;) {
+            int c1 = min(nb, c0 + S);
+            // this lane's samples in the chunk, and the cells they read
+            const int s0 = max(c0, rr.n0), s1 = min(c1 - 1, rr.n1);
+            int lo0 = INT_MAX, lo1 = INT_MAX, lo2 = INT_MAX, hi0 = INT_MIN, hi1 = INT_MIN, hi2 = INT_MIN;
+            if (s0 <= s1) {
+                const float fa = (float)(s0 - na), fb = (float)(s1 - na);
+                const float xa = __builtin_amdgcn_fmed3f(fmaf(fa, dqx, q0x), 0.f, A.fn1[0]);
+                const float ya = __builtin_amdgcn_fmed3f(fmaf(fa, dqy, q0y), 0.f, A.fn1[1]);
+                const float za = __builtin_amdgcn_fmed3f(fmaf(fa, dqz, q0z), 0.f, A.fn1[2]);
+                const float xb = __builtin_amdgcn_fmed3f(fmaf(fb, dqx, q0x), 0.f, A.fn1[0]);
+                const float yb = __builtin_amdgcn_fmed3f(fmaf(fb, dqy, q0y), 0.f, A.fn1[1]);
+                const float zb = __builtin_amdgcn_fmed3f(fmaf(fb, dqz, q0z), 0.f, A.fn1[2]);
+                lo0 = (int)fminf(xa, xb);
+                lo1 = (int)fminf(ya, yb);
+                lo2 = (int)fminf(za, zb);
+                hi0 = (int)fmaxf(xa, xb) + 1;
+                hi1 = (int)fmaxf(ya, yb) + 1;
+                hi2 = (int)fmaxf(za, zb) + 1;
+            }
+            lo0 = __ockl_wfred_min_i32(lo0);
+            lo1 = __ockl_wfred_min_i32(lo1);
+            lo2 = __ockl_wfred_min_i32(lo2);
+            hi0 = __ockl_wfred_max_i32(hi0);
+            hi1 = __ockl_wfred_max_i32(hi1);
+            hi2 = __ockl_wfred_max_i32(hi2);
+            if (lo0 > hi0) {        // no lane samples this chunk
+                c0 = c1;
+                continue;
+            }
+            const int dx = hi0 - lo0 + 1, dy = hi1 - lo1 + 1, dz = hi2 - lo2 + 1;
+            const int dxy = dx * dy, cells = dxy * dz;
+            if (cells > BUF && S > 4) {
+                S >>= 1;             // retry a shorter chunk
+                continue;
+            }
+            if (cells > BUF) {
+                // the rays spread too far for the buffer even over 4 samples
+                // (coarse detectors): gather the rest through the L1
+                gather = true;
+                c1 = nb;
+            }
+            const bool staged = !gather;
+            if (staged) {
+                // every lane is past the previous chunk's reads (the wave runs
+                // in order); copy the box, rows along the fastest axis
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                // cell e = row dx + lx, row = lz dy + ly: each lane starts at
+                // e = lane and advances by 64 cells (64 / dx rows and 64 % dx
+                // cells); quotients from rounded reciprocals, then corrected
+                // (off by at most one)
+                const float idx_ = 1.0f / (float)dx, idy_ = 1.0f / (float)dy;
+                const int srow = 64 / dx, sx = 64 - srow * dx;
+                int row = (int)(((float)lane + 0.5f) * idx_);
+                int lx = lane - row * dx;
+                if (lx < 0) { --row; lx += dx; } else if (lx >= dx) { ++row; lx -= dx; }
+                for (int e = lane; e < cells; e += 64) {
+                    int lz = (int)(((float)row + 0.5f) * idy_);
+                    int ly = row - lz * dy;
+                    if (ly < 0) { --lz; ly += dy; } else if (ly >= dy) { ++lz; ly -= dy; }
+                    const int goff = (lo0 + lx) * CB + (int)__umul24(__umul24(lo2 + lz, PY) + lo1 + ly, YS);
+                    stage_cell<C>(vb + goff, st + e * C);
+                    lx += sx;
+                    row += srow;
+                    if (lx >= dx) { lx -= dx; ++row; }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            // the chunk's samples: the same positions, weights and order as
+            // in k_march_f32; a lane reloads its cells only when they change
+            auto step = [&](int n, auto&& load) {
+                ++nsamp;
+                const float fm = (float)(n - na);
+                float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
+                float qy = __builtin_amdgcn_fmed3f(fmaf(fm, dqy, q0y), 0.f, A.fn1[1]);
+                float qz = __builtin_amdgcn_fmed3f(fmaf(fm, dqz, q0z), 0.f, A.fn1[2]);
+                const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
+                const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
+                            az = __builtin_amdgcn_fractf(qz);
+                load(ix, iy, iz);
+                const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
+                const float w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
+                const float w000 = bx * w00, w100 = ax * w00, w010 = bx * w10, w110 = ax * w10;
+                const float w001 = bx * w01, w101 = ax * w01, w011 = bx * w11, w111 = ax * w11;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    float t = acc[c];
+                    t = fmaf(w000, p00.a[c], t);
+                    t = fmaf(w100, p00.b[c], t);
+                    t = fmaf(w010, p10.a[c], t);
+                    t = fmaf(w110, p10.b[c], t);
+                    t = fmaf(w001, p01.a[c], t);
+                    t = fmaf(w101, p01.b[c], t);
+                    t = fmaf(w011, p11.a[c], t);
+                    t = fmaf(w111, p11.b[c], t);
+                    acc[c] = t;
+                }
+            };
+            int last = -1;
+            const int s_lo = max(c0, rr.n0), s_hi = min(c1 - 1, rr.n1);
+            if (staged) {
+                const int base = (lo2 * dy + lo1) * dx + lo0;
+                for (int n = s_lo; n <= s_hi; ++n)
+                    step(n, [&](int ix, int iy, int iz) {
+                        const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
+                        if (loc != last) {
+                            last = loc;
+                            lds_pair<C>(st, loc, p00.a, p00.b);
+                            lds_pair<C>(st, loc + dx, p10.a, p10.b);
+                            lds_pair<C>(st, loc + dxy, p01.a, p01.b);
+                            lds_pair<C>(st, loc + dxy + dx, p11.a, p11.b);
+                        }
+                    });
+            } else {
+                for (int n = s_lo; n <= s_hi; ++n)
+                    step(n, [&](int ix, int iy, int iz) {
+                        const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
+                        if (voff != last) {
+                            last = voff;
+                            p00 = load_pair_g<C>(vb, voff);
+                            p10 = load_pair_g<C>(vb, voff + YS);
+                            p01 = load_pair_g<C>(vb, voff + ZS);
+                            p11 = load_pair_g<C>(vb, voff + YZ);
+                        }
+                    });
+            }
+            if (cells * 3 < BUF && S < 64) S <<= 1;
+            c0 = c1;
+        }
+    }
+    if (A.ms.seg > 1) {
+        __syncthreads();   // every wave is done with its staging buffer
+        float* segbuf = (float*)smem;
+#pragma unroll
+        for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
+        __syncthreads();
+        if (sid == 0)
+            for (int s2 = 1; s2 < A.ms.seg; ++s2)
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
+    }
+    const bool owner = valid && sid == 0;
+    const float dt = (float)g.dt;
+    if (owner && A.p_out) A.p_out[iu + (size_t)g.nu * iv] = dt * acc[0];
+    if (A.partials) {
         constexpr int NM = 5 + 3 * (C - 1);
         double mo[NM + 1];
 #pragma unroll
@@ -1501,9 +1803,9 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
         if (b.hi[a] <= b.lo[a]) return hipSuccess;   // nothing to compute
     }
     const int ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
-    dim3 grid((ex + 63) / 64, (ey + 3) / 4, ez), blk(64, 4);
+    dim3 grid((ex + 255) / 256, ey, ez), blk(256, 1);
     auto w = wvec(w_eff, K);
-    dim3 grid_yf((ex + 31) / 32, (ey + 31) / 32, ez);
+    dim3 grid_yf((ex + 127) / 128, (ey + 7) / 8, ez);
     Chan<float, 8> hs;
     for (int c = 0; c < 8; ++c) hs.v[c] = L.hs[c];
 #define PCR_WF2(C, T, H)                                                                          \
@@ -1649,16 +1951,24 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
     A.moments = moments;
     int blocks = march_blocks(rg, ms);
     if (L.half && L.C == 1) return hipErrorInvalidValue;
-#define PCR_MF(C)                                                                                 \
-    (L.half ? k_march_f32<C, true><<<blocks, 256, 0, s>>>(A) : k_march_f32<C, false><<<blocks, 256, 0, s>>>(A))
-    switch (L.C) {
-    case 1: k_march_f32<1, false><<<blocks, 256, 0, s>>>(A); break;
-    case 2: PCR_MF(2); break;
-    case 4: PCR_MF(4); break;
-    case 8: PCR_MF(8); break;
-    default: return hipErrorInvalidValue;
+    if (L.half) {
+        switch (L.C) {
+        case 2: k_march_f32<2, true><<<blocks, 256, 0, s>>>(A); break;
+        case 4: k_march_f32<4, true><<<blocks, 256, 0, s>>>(A); break;
+        case 8: k_march_f32<8, true><<<blocks, 256, 0, s>>>(A); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        // 8-byte cells (C = 2) gather well enough through the L1: there the
+        // staging costs more than it saves (measured)
+        switch (L.C) {
+        case 1: k_march_lds<1><<<blocks, 256, 0, s>>>(A); break;
+        case 2: k_march_f32<2, false><<<blocks, 256, 0, s>>>(A); break;
+        case 4: k_march_lds<4><<<blocks, 256, 0, s>>>(A); break;
+        case 8: k_march_lds<8><<<blocks, 256, 0, s>>>(A); break;
+        default: return hipErrorInvalidValue;
+        }
     }
-#undef PCR_MF
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !moments) return e;
     return run_reduce(partials, blocks, n_moments(kc), n_moments(L.C), moments, s, done, seq);

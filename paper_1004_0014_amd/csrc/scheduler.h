@@ -8,9 +8,12 @@
 // executors in CPU tests.
 //
 // Executor interface (duck-typed):
-//   bool start(int slot, const Request& r, int sid, const double* w0, double mu0);
-//       begin a solve in `slot`; false if it could not start (the executor
-//       then reports the failure from the next advance()).
+//   bool start(int slot, const Request& r, int sid, const double* w0, double mu0,
+//              double move);
+//       begin a solve in `slot` (mu0 > 0: its first trial's step size; move
+//       >= 0: the distance the stream's previous solve moved w, from which
+//       the first trial's distance is set); false if it could not start (the
+//       executor then reports the failure from the next advance()).
 //   int advance(int slot, pcr_result* res);
 //       0: nothing new; 1: progressed, still running; 2: finished, `res`
 //       holds status, iterations, trials, w, ab, J, tumour, mu0, mu (the
@@ -78,6 +81,7 @@ struct StreamState {
     double hist_t[3];
     int nhist = 0;
     double mu_last = 0;      // step size the last solve ended with
+    double move_last = -1;   // distance the last solve moved w (< 0: none yet)
     size_t bytes = 0;        // device bytes of the stream's own data
     size_t scratch = 0;      // slot scratch its solves need
 };
@@ -88,6 +92,7 @@ struct Options {
     bool drop_stale = true;
     int predict_order = 0;
     bool chain_step = false;
+    bool carry_move = false;
 };
 
 template <class Exec>
@@ -266,6 +271,7 @@ class Core {
         for (int k = 0; k < it->second.K; ++k) it->second.w[k] = w[k];
         it->second.nhist = 0;
         it->second.mu_last = 0;
+        it->second.move_last = -1;
         return PCR_OK;
     }
     int stream_K(int sid) const
@@ -310,6 +316,7 @@ class Core {
         Request req;
         double w0[8];
         double mu0;
+        double move;
     };
 
     // Under the lock: free slots take the oldest queued requests of idle
@@ -330,6 +337,7 @@ class Core {
             for (int k = 0; k < 8; ++k) f.w0[k] = st.w[k];
             if (o_.predict_order > 0 && st.nhist >= 2) predict(st, it->t_submit, f.w0);
             f.mu0 = (o_.chain_step && st.mu_last > 0) ? st.mu_last : 0.0;
+            f.move = o_.carry_move ? st.move_last : -1.0;
             st.active = true;
             st.queued--;
             slot_busy_[s] = 1;
@@ -357,8 +365,14 @@ class Core {
         res.t_done_s = now_s();
         for (int k = 0; k < 8; ++k) res.w0[k] = k < st.K ? slot_w0_[s][k] : 0.0;
         if (res.status == PCR_OK || res.status == PCR_ENOCONV) {
+            double m2 = 0.0;
+            for (int k = 0; k < st.K; ++k) {
+                const double d = res.w[k] - slot_w0_[s][k];
+                m2 += d * d;
+            }
             for (int k = 0; k < st.K; ++k) st.w[k] = res.w[k];
             st.mu_last = res.mu;
+            st.move_last = std::sqrt(m2);
             if (st.nhist == 3) {
                 for (int i = 0; i < 2; ++i) {
                     st.hist_t[i] = st.hist_t[i + 1];
@@ -394,7 +408,7 @@ class Core {
                 dispatch(fresh);
             }
             for (const Fresh& f : fresh) {
-                if (!ex_.start(f.slot, f.req, f.req.sid, f.w0, f.mu0)) {
+                if (!ex_.start(f.slot, f.req, f.req.sid, f.w0, f.mu0, f.move)) {
                     pcr_result res;
                     std::memset(&res, 0, sizeof res);
                     if (ex_.advance(f.slot, &res) != 2) res.status = PCR_EDEVICE;

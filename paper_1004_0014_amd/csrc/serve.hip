@@ -52,6 +52,7 @@ struct Slot {
     bool pending = false;     // an evaluation is enqueued
     pcr_status err = PCR_OK;  // a failure to start, reported by the next advance()
     double mu0 = 0;           // first trial step of the solve (0: the default rule)
+    double step0 = 0;         // first trial distance (when mu0 is 0)
     StreamDev* st = nullptr;
     Evaluator E{};
     SolveSM sm;
@@ -78,14 +79,15 @@ struct HipExec {
     std::map<int, std::unique_ptr<StreamDev>> streams;
     size_t max_image = 0;   // largest fused image (FP32 cells) of an admitted stream
 
-    bool start(int slot, const sched::Request& r, int sid, const double* w0, double mu0);
+    bool start(int slot, const sched::Request& r, int sid, const double* w0, double mu0, double move);
     int advance(int slot, pcr_result* res);
     void wait_any();
     void forget_stream(int sid);
 };
 
 // Binds a slot's evaluator to its request and enqueues the first projection.
-bool HipExec::start(int slot, const sched::Request& r, int sid, const double* w0, double mu0)
+bool HipExec::start(int slot, const sched::Request& r, int sid, const double* w0, double mu0,
+                    double move)
 {
     Slot& sl = *slots[slot];
     sl.pending = false;
@@ -111,7 +113,9 @@ bool HipExec::start(int slot, const sched::Request& r, int sid, const double* w0
     if (e == PCR_OK) {
         pcr_solve_opts so = st->opts;
         if (mu0 > 0) so.mu0 = mu0;
+        if (move >= 0) so.step0 = std::min(std::max(move, 1e-3 * so.step0), so.step0);
         sl.mu0 = so.mu0;
+        sl.step0 = so.mu0 > 0 ? 0.0 : so.step0;
         sl.sm.begin(st->model.K, so, st->model.scale ? st->scale : nullptr, w0);
         e = sl.E.enqueue_eval(sl.sm.eval_w());
     }
@@ -179,6 +183,7 @@ int HipExec::advance(int slot, pcr_result* res)
     res->ab[0] = sl.sm.a;
     res->ab[1] = sl.sm.b;
     res->mu0 = sl.mu0;
+    res->step0 = sl.step0;
     res->mu = sl.sm.mu;
     res->samples = sl.sm.samples;
     for (int k = 0; k < st->model.K; ++k) res->w[k] = sl.sm.w[k];
@@ -233,6 +238,7 @@ sched::Options core_options(const pcr_server_opts& o)
     c.drop_stale = o.drop_stale != 0;
     c.predict_order = o.predict_order;
     c.chain_step = o.chain_step != 0;
+    c.carry_move = o.carry_move != 0;
     return c;
 }
 
@@ -253,6 +259,8 @@ pcr_status pcr_server_create(const pcr_server_opts* opts, pcr_server** out)
     if (opts->max_slots < 1 || opts->max_slots > 64) return fail(PCR_EINVAL, "max_slots must be in 1..64");
     if (opts->predict_order < 0 || opts->predict_order > 2) return fail(PCR_EINVAL, "predict_order must be 0..2");
     if (opts->hbm_budget_bytes == 0) return fail(PCR_EINVAL, "hbm_budget_bytes must be > 0");
+    if (opts->chain_step && opts->carry_move)
+        return fail(PCR_EINVAL, "chain_step and carry_move are alternatives: set one");
     auto S = std::make_unique<pcr_server>();
     S->o = *opts;
     HIP_TRY(hipGetDevice(&S->ex.device));

@@ -8,7 +8,8 @@ nu ~ U{256..1024} (multiples of 32), nv = 3/4 nu, 397 mm / nu pitch, one
 projection every 1/11 s with N(0, 10 ms) jitter, gantry angle advancing at
 6 deg/s from a seeded start (one rotation per minute, section 3), breathing
 at 1.5x the training amplitude with a 4 s period.  Reference images and
-eigenvector fields are stored BF16 on the device; compute is FP32.
+eigenvector fields are stored BF16 on the device (FP32 with --storage f32);
+compute is FP32.
 
 Inputs are synthesised on the GPU with plain torch ops (ellipsoid thorax,
 smoothed Gaussian texture, the analytic rank-K breathing motion and its PCA
@@ -21,6 +22,7 @@ of the truth-warped FP32 phantom.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import math
 import sys
@@ -129,10 +131,12 @@ def truth_w(pca, K, phi, scale=1.5):
 
 
 class SimStream:
-    """One patient stream: BF16 model and reference image, request schedule and
+    """One patient stream: model and reference image stored in `storage`
+    (BF16 by default; FP32 keeps them as built), request schedule and
     measured projections (FP32, on the device)."""
 
-    def __init__(self, idx, seed, seconds, dev, rate_hz=11.0, jitter_s=0.010):
+    def __init__(self, idx, seed, seconds, dev, rate_hz=11.0, jitter_s=0.010,
+                 storage=torch.bfloat16):
         rng = np.random.default_rng([seed, idx])
         sp = stream_spec(rng)
         self.idx, self.K, self.grid = idx, sp["K"], sp["grid"]
@@ -154,20 +158,28 @@ class SimStream:
             self.geoms.append(G)
             self.w_true.append(w)
             del dvf, f
-        self.f0 = f0.to(torch.bfloat16)
-        self.model = _lib.DeviceModel(mean.to(torch.bfloat16), U.to(torch.bfloat16))
+        self.f0 = f0.to(storage)
+        self.model = _lib.DeviceModel(mean.to(storage), U.to(storage))
         self.spec = sp
         del f0, mean, U, dm32
+
+    def as_storage(self, storage):
+        """The same stream (schedule, projections, truth) with its reference
+        image and model converted to `storage`."""
+        c = copy.copy(self)
+        c.f0 = self.f0.to(storage)
+        c.model = _lib.DeviceModel(self.model.mean.to(storage), self.model.U.to(storage))
+        return c
 
     def opts(self):
         return _lib.default_opts(max_iter=50, step0=self.pca["step0"], localize=1, p_ref_mm=self.p_ref)
 
 
-def build_streams(n_streams, seconds, seed, dev):
+def build_streams(n_streams, seconds, seed, dev, storage=torch.bfloat16):
     t0 = time.time()
     out = []
     for i in range(n_streams):
-        out.append(SimStream(i, seed, seconds, dev))
+        out.append(SimStream(i, seed, seconds, dev, storage=storage))
         if (i + 1) % 8 == 0:
             log("[serve] built %d/%d streams (%.1fs)" % (i + 1, n_streams, time.time() - t0))
     torch.cuda.synchronize()
@@ -175,9 +187,11 @@ def build_streams(n_streams, seconds, seed, dev):
 
 
 # ----------------------------------------------------------------- run -----
-def run(streams, seconds, max_slots, budget_gb, drop_stale=True, image_f16=False):
+def run(streams, seconds, max_slots, budget_gb, drop_stale=True, image_f16=False, predict_order=0,
+        carry_move=False):
     srv = _lib.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=max_slots,
-                      drop_stale=drop_stale, image_f16=image_f16)
+                      drop_stale=drop_stale, image_f16=image_f16, predict_order=predict_order,
+                      carry_move=carry_move)
     sids, rejected = [], 0
     for st in streams:
         try:
@@ -251,12 +265,20 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--image-f16", action="store_true", help="FP16 fused images")
+    ap.add_argument("--predict-order", type=int, default=0,
+                    help="warm start from the extrapolation of each stream's last results")
+    ap.add_argument("--carry-move", action="store_true",
+                    help="first trial moves w by the distance the stream's last solve moved it")
+    ap.add_argument("--storage", default="bf16", choices=["bf16", "f32"],
+                    help="storage of the streams' reference images and models")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     counts = [int(s) for s in args.streams.split(",")]
-    streams = build_streams(max(counts), args.seconds, args.seed, dev)
+    storage = torch.bfloat16 if args.storage == "bf16" else torch.float32
+    streams = build_streams(max(counts), args.seconds, args.seed, dev, storage=storage)
     for n in counts:
-        res = run(streams[:n], args.seconds, args.slots, args.budget_gb, image_f16=args.image_f16)
+        res = run(streams[:n], args.seconds, args.slots, args.budget_gb, image_f16=args.image_f16,
+                  predict_order=args.predict_order, carry_move=args.carry_move)
         print(json.dumps({"serving": res}), flush=True)
 
 

@@ -41,6 +41,7 @@ struct StartCall {
     int64_t req;
     double w0[8];
     double mu0;
+    double move;
 };
 
 struct FakeExec {
@@ -60,14 +61,14 @@ struct FakeExec {
 
     explicit FakeExec(int n) : slots(n) {}
 
-    bool start(int slot, const Request& r, int sid, const double* w0, double mu0)
+    bool start(int slot, const Request& r, int sid, const double* w0, double mu0, double move)
     {
         std::lock_guard<std::mutex> lk(m);
         S& s = slots[slot];
         CHECK(!s.on);
         for (const S& o : slots)
             if (o.on && o.sid == sid) overlap_seen = true;
-        StartCall c{slot, sid, r.id, {0}, mu0};
+        StartCall c{slot, sid, r.id, {0}, mu0, move};
         for (int k = 0; k < 8; ++k) c.w0[k] = w0[k];
         starts.push_back(c);
         s.f = static_cast<const Frame*>(r.y);
@@ -441,6 +442,40 @@ void test_predict_and_chain()
     CHECK(r3[0].w0[0] == 9 && r3[0].w0[1] == 9 && r3[0].mu0 == 0.0);
 }
 
+void test_carry_move()
+{
+    // carry_move: each solve starts with the distance the stream's previous
+    // solve moved w (none before the first, and none after set_w)
+    Options o = opts(1);
+    o.carry_move = true;
+    Server s(o);
+    const double z[2] = {0, 0};
+    const int A = add(s.core, 2, z);
+    Frame f[4];
+    for (int i = 0; i < 4; ++i) {
+        f[i].w[0] = 3.0 * i + 1.0;
+        f[i].w[1] = 4.0 * i * i;
+    }
+    int64_t r[4];
+    for (int i = 0; i < 3; ++i) {
+        CHECK(s.core.submit(A, &f[i], geom0(), &r[i]) == PCR_OK);
+        CHECK(s.core.drain(5000));
+    }
+    auto c = s.ex.calls();
+    CHECK(c.size() == 3);
+    CHECK(c[0].move < 0);
+    // solve 0 moved w from (0, 0) to (1, 0); solve 1 from (1, 0) to (4, 4)
+    CHECK(std::fabs(c[1].move - 1.0) <= 1e-12);
+    CHECK(std::fabs(c[2].move - 5.0) <= 1e-12);
+    for (const auto& k : c) CHECK(k.mu0 == 0.0);
+    collect(s.core, 3);
+    const double wn[2] = {9, 9};
+    CHECK(s.core.set_w(A, wn) == PCR_OK);
+    CHECK(s.core.submit(A, &f[3], geom0(), &r[3]) == PCR_OK);
+    CHECK(s.core.drain(5000));
+    CHECK(s.ex.calls().back().move < 0);
+}
+
 void test_set_w_busy_and_stop()
 {
     Server s(opts(1));
@@ -463,6 +498,7 @@ void test_set_w_busy_and_stop()
 int main()
 {
     test_extrapolate();
+    test_carry_move();
     test_admission();
     test_order_and_warm_start();
     test_slot_reuse();

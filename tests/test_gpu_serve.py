@@ -209,3 +209,35 @@ def test_chained_step_size(streams):
     assert w == res[2]["w"] and sta["trials"] == res[2]["trials"]
     assert sta["mu"] == res[2]["mu"]
     srv.close()
+
+
+def test_carried_move_with_predicted_start(streams):
+    """With carry_move (and a predicted warm start) each solve's first trial
+    moves w by the distance the stream's previous solve moved it, clamped to
+    [1e-3, 1] x step0; the result equals a blocking solve given the same
+    start and step0."""
+    L = _L()
+    st = streams[1]
+    srv = L.Server(hbm_budget_bytes=4 << 30, max_slots=1, predict_order=1, carry_move=True)
+    sid = srv.add_stream(st.grid, st.dm, st.df0, st.opts, np.zeros(st.K))
+    res = []
+    for j in range(3):
+        srv.submit(sid, st.ys[j], st.geoms[j])
+        srv.drain()
+        res += srv.poll(4)
+    assert [r["status"] in (0, -4) for r in res] == [True] * 3
+    s0 = st.m.step0
+    assert res[0]["step0"] == s0
+    for prev, cur in zip(res, res[1:]):
+        move = float(np.linalg.norm(np.array(prev["w"]) - np.array(prev["w0"])))
+        assert abs(cur["step0"] - min(max(move, 1e-3 * s0), s0)) <= 1e-12 * s0
+        assert cur["mu0"] == 0.0
+    ctx = L.Context(st.grid, st.dm, st.df0)
+    opts = L.default_opts(max_iter=25, step0=res[2]["step0"], localize=1,
+                          p_ref_mm=S.tumor_center(st.grid))
+    w, ab, sta = ctx.reconstruct(st.ys[2], st.geoms[2], res[2]["w0"], opts)
+    ctx.close()
+    assert w == res[2]["w"] and sta["trials"] == res[2]["trials"]
+    srv.close()
+    with pytest.raises(L.PCRError):
+        L.Server(hbm_budget_bytes=4 << 30, max_slots=1, chain_step=True, carry_move=True)
