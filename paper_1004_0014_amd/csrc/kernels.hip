@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 // grows the next chunk.  Each staged cell serves ~40 sample taps at paper
 // scale, so the L1 sees a few coalesced row loads per chunk instead of 8
 // scattered cells per sample.
-constexpr int kStageBytes = 8192;     // LDS per wave
+constexpr int kStageBytes = 9216;     // LDS per wave: four 256-thread blocks per CU
 
 // Cells `cell` and `cell` + 1 of a staging buffer of C-float cells.
 template <int C>
@@ -977,9 +977,40 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             p00.a[c] = p00.b[c] = p10.a[c] = p10.b[c] = 0.f;
             p01.a[c] = p01.b[c] = p11.a[c] = p11.b[c] = 0.f;
         }
+        // the chunk's samples: the same positions, weights and order as
+        // in k_march_f32; a lane reloads its cells only when they change
+        auto step = [&](int n, auto&& load) {
+            ++nsamp;
+            const float fm = (float)(n - na);
+            float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
+            float qy = __builtin_amdgcn_fmed3f(fmaf(fm, dqy, q0y), 0.f, A.fn1[1]);
+            float qz = __builtin_amdgcn_fmed3f(fmaf(fm, dqz, q0z), 0.f, A.fn1[2]);
+            const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
+            const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
+                        az = __builtin_amdgcn_fractf(qz);
+            load(ix, iy, iz);
+            const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
+            const float w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
+            const float w000 = bx * w00, w100 = ax * w00, w010 = bx * w10, w110 = ax * w10;
+            const float w001 = bx * w01, w101 = ax * w01, w011 = bx * w11, w111 = ax * w11;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float t = acc[c];
+                t = fmaf(w000, p00.a[c], t);
+                t = fmaf(w100, p00.b[c], t);
+                t = fmaf(w010, p10.a[c], t);
+                t = fmaf(w110, p10.b[c], t);
+                t = fmaf(w001, p01.a[c], t);
+                t = fmaf(w101, p01.b[c], t);
+                t = fmaf(w011, p11.a[c], t);
+                t = fmaf(w111, p11.b[c], t);
+                acc[c] = t;
+            }
+        };
         int S = 16;
         bool gather = false;   // the rest of the range through the L1
-        for (int c0 = na; c0 < nb;) {
+        int c0 = na;
+        while (c0 < nb) {
             int c1 = min(nb, c0 + S);
             // this lane's samples in the chunk, and the cells they read
             const int s0 = max(c0, rr.n0), s1 = min(c1 - 1, rr.n1);
@@ -1019,10 +1050,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 // the rays spread too far for the buffer even over 4 samples
                 // (coarse detectors): gather the rest through the L1
                 gather = true;
-                c1 = nb;
+                break;
             }
-            const bool staged = !gather;
-            if (staged) {
+            {
                 // every lane is past the previous chunk's reads (the wave runs
                 // in order); copy the box, rows along the fastest axis
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1050,66 +1080,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            // the chunk's samples: the same positions, weights and order as
-            // in k_march_f32; a lane reloads its cells only when they change
-            auto step = [&](int n, auto&& load) {
-                ++nsamp;
-                const float fm = (float)(n - na);
-                float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
-                float qy = __builtin_amdgcn_fmed3f(fmaf(fm, dqy, q0y), 0.f, A.fn1[1]);
-                float qz = __builtin_amdgcn_fmed3f(fmaf(fm, dqz, q0z), 0.f, A.fn1[2]);
-                const int ix = (int)qx, iy = (int)qy, iz = (int)qz;
-                const float ax = __builtin_amdgcn_fractf(qx), ay = __builtin_amdgcn_fractf(qy),
-                            az = __builtin_amdgcn_fractf(qz);
-                load(ix, iy, iz);
-                const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
-                const float w00 = by * bz, w10 = ay * bz, w01 = by * az, w11 = ay * az;
-                const float w000 = bx * w00, w100 = ax * w00, w010 = bx * w10, w110 = ax * w10;
-                const float w001 = bx * w01, w101 = ax * w01, w011 = bx * w11, w111 = ax * w11;
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    float t = acc[c];
-                    t = fmaf(w000, p00.a[c], t);
-                    t = fmaf(w100, p00.b[c], t);
-                    t = fmaf(w010, p10.a[c], t);
-                    t = fmaf(w110, p10.b[c], t);
-                    t = fmaf(w001, p01.a[c], t);
-                    t = fmaf(w101, p01.b[c], t);
-                    t = fmaf(w011, p11.a[c], t);
-                    t = fmaf(w111, p11.b[c], t);
-                    acc[c] = t;
-                }
-            };
             int last = -1;
             const int s_lo = max(c0, rr.n0), s_hi = min(c1 - 1, rr.n1);
-            if (staged) {
-                const int base = (lo2 * dy + lo1) * dx + lo0;
-                for (int n = s_lo; n <= s_hi; ++n)
-                    step(n, [&](int ix, int iy, int iz) {
-                        const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
-                        if (loc != last) {
-                            last = loc;
-                            lds_pair<C>(st, loc, p00.a, p00.b);
-                            lds_pair<C>(st, loc + dx, p10.a, p10.b);
-                            lds_pair<C>(st, loc + dxy, p01.a, p01.b);
-                            lds_pair<C>(st, loc + dxy + dx, p11.a, p11.b);
-                        }
-                    });
-            } else {
-                for (int n = s_lo; n <= s_hi; ++n)
-                    step(n, [&](int ix, int iy, int iz) {
-                        const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
-                        if (voff != last) {
-                            last = voff;
-                            p00 = load_pair_g<C>(vb, voff);
-                            p10 = load_pair_g<C>(vb, voff + YS);
-                            p01 = load_pair_g<C>(vb, voff + ZS);
-                            p11 = load_pair_g<C>(vb, voff + YZ);
-                        }
-                    });
-            }
+            const int base = (lo2 * dy + lo1) * dx + lo0;
+            for (int n = s_lo; n <= s_hi; ++n)
+                step(n, [&](int ix, int iy, int iz) {
+                    const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
+                    if (loc != last) {
+                        last = loc;
+                        lds_pair<C>(st, loc, p00.a, p00.b);
+                        lds_pair<C>(st, loc + dx, p10.a, p10.b);
+                        lds_pair<C>(st, loc + dxy, p01.a, p01.b);
+                        lds_pair<C>(st, loc + dxy + dx, p11.a, p11.b);
+                    }
+                });
             if (cells * 3 < BUF && S < 64) S <<= 1;
             c0 = c1;
+        }
+        if (gather) {
+            int last = -1;
+            for (int n = max(c0, rr.n0); n <= min(nb - 1, rr.n1); ++n)
+                step(n, [&](int ix, int iy, int iz) {
+                    const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
+                    if (voff != last) {
+                        last = voff;
+                        p00 = load_pair_g<C>(vb, voff);
+                        p10 = load_pair_g<C>(vb, voff + YS);
+                        p01 = load_pair_g<C>(vb, voff + ZS);
+                        p11 = load_pair_g<C>(vb, voff + YZ);
+                    }
+                });
         }
     }
     if (A.ms.seg > 1) {
