@@ -1270,7 +1270,9 @@ __device__ __forceinline__ void footprint(const BPFoot& F, const float lo[3], co
         const float b = F.b0 + F.bn[0] * X + F.bn[1] * Y + F.bn[2] * Z;
         const float cc = F.c0 + F.cn[0] * X + F.cn[1] * Y + F.cn[2] * Z;
         front = front && a > 1e-3f;
-        const float t = F.sdd / a;
+        // the boxes are widened by at least 0.02 pixels, far beyond the
+        // error of the hardware reciprocal
+        const float t = F.sdd * __builtin_amdgcn_rcpf(a);
         const float u = fmaf(t, b, F.su), v = fmaf(t, cc, F.sv);
         umin = fminf(umin, u);
         umax = fmaxf(umax, u);
@@ -1295,6 +1297,12 @@ struct BPArgs {
     int nbx, nby;         // bricks per axis
     int nx, ny, nz;
     double a, b, scale;   // r = scale (p - a y - b) when no residual is given
+    double inv_dt;        // 1 / sample spacing
+};
+
+template <typename R>
+struct alignas(4 * sizeof(R)) BPVec4 {
+    R x, y, z, w;
 };
 
 template <typename R>
@@ -1303,28 +1311,38 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
                                                              const R* __restrict__ y,
                                                              R* __restrict__ out)
 {
-    __shared__ R s_q[3][256];      // nearest sample to the brick centre, minus the brick origin
-    __shared__ R s_d[3][256];      // index-space step per sample
-    // slab bounds in samples across the column (slot 0: axis B, slot 1: z):
-    // |q_a + m d_a - l| < 1 for m in (lo_a + l inv_a, hi_a + l inv_a); along
-    // A the whole column (-1, 16)
-    __shared__ float s_inv[2][256], s_lo[2][256], s_hi[2][256], s_la[256], s_ha[256];
-    __shared__ R s_rw[256];        // r dt
-    __shared__ int s_m[2][256];    // valid sample offsets [m0, m1] from that sample
-    // thread (lane, column): 16 voxels along A at [2, 18) of a run of 21
+    // One staged ray in four 16-byte records (two 32-byte ones in FP64), read
+    // with one wide load each; consecutive rays sit in consecutive records,
+    // so the lanes of a column, which take consecutive rays, read without
+    // bank conflicts.  Axes in column order (A, B, z):
+    //   s_r0: the sample nearest the brick centre minus the brick origin, r dt
+    //   s_r1: the index-space step per sample, slab lower bound along A
+    //   s_r2: slab upper bound along A; lo, hi, 1/step across the column in B
+    //   s_r3: lo, hi, 1/step across the column in z
+    // Slab bounds are in samples: |q_a + m d_a - l| < 1 for m in
+    // (lo_a + l inv_a, hi_a + l inv_a); along A the whole column (-1, 16),
+    // narrowed to the ray's valid samples.
+    __shared__ BPVec4<R> s_r0[256], s_r1[256];
+    __shared__ float4 s_r2[256], s_r3[256];
+    // thread t's run of 21 accumulators: 16 voxels along A at slots [2, 18)
     // (two pad slots each side take the clipped weights of samples just
-    // outside the column, so the accumulation needs no branch)
-    __shared__ R s_acc[256 * 21];
+    // outside the column, so the accumulation needs no branch); slot-major,
+    // slot s of thread t at s * 256 + t, so each slot of the 64 lanes of a
+    // wave spans all banks and a lane's bank does not depend on the slot:
+    // the read-modify-writes never conflict
+    __shared__ R s_acc[21 * 256];
     __shared__ int s_box[4];
     const RayGeom& g = A.g;
     const int t = threadIdx.x;
     const int bid = blockIdx.x;
     const int b0[3] = {(bid % A.nbx) * A.bx, ((bid / A.nbx) % A.nby) * A.by, (bid / (A.nbx * A.nby)) * A.bz};
     const int AX = A.ax, BX = 1 - A.ax;           // column axis and the other in-plane axis
-    const int col = t & 15, lane = t >> 4;        // column (lb, lz) and ray lane
+    // a wave holds 4 columns x 16 lanes: consecutive lanes take consecutive
+    // rays of one column, so their record loads hit distinct banks
+    const int col = t >> 4, lane = t & 15;        // column (lb, lz) and ray lane
     const int lb = col & 3, lz = col >> 2;
     for (int e = t; e < 256 * 21; e += 256) s_acc[e] = (R)0;
-    R* acc = s_acc + (lane * 16 + col) * 21 + 2;
+    R* acc = s_acc + 2 * 256 + t;
     if (t == 0) {
         const float lo[3] = {(float)(b0[0] - 1), (float)(b0[1] - 1), (float)(b0[2] - 1)};
         const float hi[3] = {(float)(b0[0] + A.bx), (float)(b0[1] + A.by), (float)(b0[2] + A.bz)};
@@ -1373,15 +1391,23 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
                         L2 += w * w;
                     }
                     if (L2 > 0.0 && r != 0.0) {
-                        const double L = sqrt(L2), invL = 1.0 / L;
+                        // 1/L from the hardware reciprocal square root and two
+                        // Newton steps (each doubles the correct bits)
+                        double invL = __builtin_amdgcn_rsq(L2);
+                        invL = fma(0.5 * invL, fma(-L2 * invL, invL, 1.0), invL);
+                        invL = fma(0.5 * invL, fma(-L2 * invL, invL, 1.0), invL);
+                        const double L = L2 * invL;
                         double tc = 0.0;
 #pragma unroll
                         for (int ax = 0; ax < 3; ++ax) {
                             D[ax] *= invL;   // index units per mm
                             tc += (cb[ax] - g.qs[ax]) * g.sp[ax] * g.sp[ax] * D[ax];
                         }
-                        const double nlast = floor(L / g.dt);
-                        const double nc = fmin(fmax(rint(tc / g.dt), 0.0), nlast);
+                        // the last sample lies at the detector, far outside the
+                        // volume, and the centre sample only anchors m: neither
+                        // needs a correctly rounded quotient
+                        const double nlast = floor(L * A.inv_dt);
+                        const double nc = fmin(fmax(rint(tc * A.inv_dt), 0.0), nlast);
                         const double tn = nc * g.dt;
 #pragma unroll
                         for (int ax = 0; ax < 3; ++ax) {
@@ -1393,28 +1419,26 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
                         rw = (R)(r * g.dt);
                     }
                 }
+                float lo[3], hi[3], inv[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    s_q[ax][t] = (R)qr[ax];
-                    s_d[ax][t] = (R)dq[ax];
                     const float df = (float)dq[ax];
-                    const float inv = fabsf(df) > 1e-30f ? 1.0f / df : 1.0e30f;
-                    const float e1 = (-1.0f - (float)qr[ax]) * inv;
-                    if (ax == AX) {
-                        const float e3 = (16.0f - (float)qr[ax]) * inv;
-                        s_la[t] = fminf(e1, e3);
-                        s_ha[t] = fmaxf(e1, e3);
-                    } else {
-                        const float e2 = (1.0f - (float)qr[ax]) * inv;
-                        const int sl = ax == 2 ? 1 : 0;
-                        s_inv[sl][t] = inv;
-                        s_lo[sl][t] = fminf(e1, e2);
-                        s_hi[sl][t] = fmaxf(e1, e2);
-                    }
+                    // the slab bounds carry a 1e-3 sample slack, so the
+                    // hardware reciprocal (1 ulp) is exact enough
+                    inv[ax] = fabsf(df) > 1e-30f ? __builtin_amdgcn_rcpf(df) : 1.0e30f;
+                    const float e1 = (-1.0f - (float)qr[ax]) * inv[ax];
+                    const float e2 = ((ax == AX ? 16.0f : 1.0f) - (float)qr[ax]) * inv[ax];
+                    lo[ax] = fminf(e1, e2);
+                    hi[ax] = fmaxf(e1, e2);
                 }
-                s_rw[t] = rw;
-                s_m[0][t] = m0;
-                s_m[1][t] = m1;
+                // the valid samples [m0, m1] narrow the bounds along A: with
+                // the half-sample margin the rounding below yields exactly
+                // max(m0, .) and min(m1, .) (|m| < 2^22 where they bind)
+                const float la = fmaxf(lo[AX], (float)m0 - 0.5f), ha = fminf(hi[AX], (float)m1 + 0.5f);
+                s_r0[t] = {(R)qr[AX], (R)qr[BX], (R)qr[2], rw};
+                s_r1[t] = {(R)dq[AX], (R)dq[BX], (R)dq[2], (R)la};
+                s_r2[t] = make_float4(ha, lo[BX], hi[BX], inv[BX]);
+                s_r3[t] = make_float4(lo[2], hi[2], inv[2], 0.0f);
             }
             __syncthreads();
             // rays of this tile inside the column's footprint, split over the
@@ -1443,19 +1467,25 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
                 // samples within one voxel of the column line (slab test; the
                 // 1e-3 sample slack covers the FP32 rounding of the bounds and
                 // the weights clip any sample it admits)
-                const float ib = s_inv[0][k], iz = s_inv[1][k];
-                float lo = fmaxf(fmaxf(s_la[k], fmaf(flb, ib, s_lo[0][k])), fmaf(flz, iz, s_lo[1][k]));
-                float hi = fminf(fminf(s_ha[k], fmaf(flb, ib, s_hi[0][k])), fmaf(flz, iz, s_hi[1][k]));
+                const BPVec4<R> r0 = s_r0[k], r1 = s_r1[k];
+                const float4 r2 = s_r2[k], r3 = s_r3[k];
+                float lo = fmaxf(fmaxf((float)r1.w, fmaf(flb, r2.w, r2.y)), fmaf(flz, r3.z, r3.x));
+                float hi = fminf(fminf(r2.x, fmaf(flb, r2.w, r2.z)), fmaf(flz, r3.z, r3.y));
                 lo = fminf(fmaxf(lo, -1.0e6f), 1.0e6f);   // |m| stays far inside int range
                 hi = fminf(fmaxf(hi, -1.0e6f), 1.0e6f);
-                const int m0 = max(s_m[0][k], (int)ceilf(lo - 1.0e-3f));
-                const int m1 = min(s_m[1][k], (int)floorf(hi + 1.0e-3f));
+                const int m0 = (int)ceilf(lo - 1.0e-3f);
+                const int m1 = (int)floorf(hi + 1.0e-3f);
                 if (m0 > m1) continue;
-                const R qa = s_q[AX][k], qb = s_q[BX][k] - rlb, qz = s_q[2][k] - rlz;
-                const R da = s_d[AX][k], db = s_d[BX][k], dz = s_d[2][k];
-                const R rw = s_rw[k];
-                for (int m = m0; m <= m1; ++m) {
-                    const R fm = (R)m;
+                const R qa = r0.x, qb = r0.y - rlb, qz = r0.z - rlz;
+                const R da = r1.x, db = r1.y, dz = r1.z;
+                const R rw = r0.w;
+                // the sample index runs as a float (|m| < 1e6: exact)
+                const R fm1 = (R)m1;
+                // the ray's values are in registers before the loop starts,
+                // so no wait inside it holds back for the previous sample's
+                // LDS write
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+                for (R fm = (R)m0; fm <= fm1; fm += (R)1) {
                     const R wbz = fmax((R)0, (R)1 - fabs(fma(fm, db, qb))) *
                                   fmax((R)0, (R)1 - fabs(fma(fm, dz, qz))) * rw;
                     const R xa = fma(fm, da, qa);
@@ -1465,18 +1495,20 @@ __global__ void __launch_bounds__(256) k_backproject_columns(BPArgs A, const R* 
                     const int j = min(max((int)fl, -2), 16);
                     const R fa = xa - fl;
                     // the thread's own LDS run: a plain read-modify-write
-                    acc[j] += ((R)1 - fa) * wbz;
-                    acc[j + 1] += fa * wbz;
+                    acc[j * 256] += ((R)1 - fa) * wbz;
+                    acc[(j + 1) * 256] += fa * wbz;
                 }
             }
             __syncthreads();
         }
     }
-    // voxel (column c, position j along A): the sum over the column's 16 lanes
+    // voxel (column c, position j along A): the sum over the column's 16
+    // lanes, in an order rotated by j so that the lanes of a wave read
+    // different banks
     {
         const int c = t >> 4, j = t & 15;
         R v = (R)0;
-        for (int l = 0; l < 16; ++l) v += s_acc[(l * 16 + c) * 21 + 2 + j];
+        for (int l = 0; l < 16; ++l) v += s_acc[(2 + j) * 256 + c * 16 + ((l + j) & 15)];
         int vx[3];
         vx[AX] = b0[AX] + j;
         vx[BX] = b0[BX] + (c & 3);
@@ -2070,6 +2102,7 @@ hipError_t launch_backproject(pcr_dtype compute, const pcr_grid& g, const RayGeo
     A.a = a;
     A.b = b;
     A.scale = scale;
+    A.inv_dt = 1.0 / rg.dt;
     const long blocks = (long)A.nbx * A.nby * nbz;
     if (blocks <= 0 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     PCR_DISPATCH_R(compute, R,
