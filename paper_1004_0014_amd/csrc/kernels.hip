@@ -872,7 +872,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 // grows the next chunk.  Each staged cell serves ~40 sample taps at paper
 // scale, so the L1 sees a few coalesced row loads per chunk instead of 8
 // scattered cells per sample.
-constexpr int kStageBytes = 7168;     // LDS per wave: five 256-thread blocks per CU
+// LDS per wave: at C <= 4 five 256-thread blocks per CU; the 8-channel
+// kernel holds two blocks per CU (its registers bind), so its waves take more
+template <int C>
+constexpr int stage_bytes() { return C <= 4 ? 7168 : 16384; }
 
 // Cells `cell` and `cell` + 1 of a staging buffer of C-float cells.
 template <int C>
@@ -913,6 +916,7 @@ template <int C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 5 : 1))) k_march_lds(MarchArgs A)
 {
     constexpr int CB = 4 * C;                    // bytes per cell
+    constexpr int kStageBytes = stage_bytes<C>();
     constexpr int BUF = kStageBytes / CB;        // cells per wave
     const RayGeom& g = A.g;
     const int rpb = 256 / A.ms.seg;
