@@ -884,10 +884,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 // grows the next chunk.  Each staged cell serves ~40 sample taps at paper
 // scale, so the L1 sees a few coalesced row loads per chunk instead of 8
 // scattered cells per sample.
-// LDS per wave: at C <= 4 five 256-thread blocks per CU; the 8-channel
-// kernel holds two blocks per CU (its registers bind), so its waves take more
+// LDS per wave: six 256-thread blocks per CU at C <= 4 (68 VGPRs), four at
+// C = 8 (108 VGPRs), the most that the registers allow in each case
 template <int C>
-constexpr int stage_bytes() { return C <= 4 ? 7168 : 16384; }
+constexpr int stage_bytes() { return C <= 4 ? 6144 : 9216; }
 
 // Cells `cell` and `cell` + 1 of a staging buffer of C-float cells.
 template <int C>
@@ -925,7 +925,7 @@ __device__ __forceinline__ void stage_cell(const char* src, float* dst)
 }
 
 template <int C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 5 : 1))) k_march_lds(MarchArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 6 : 4))) k_march_lds(MarchArgs A)
 {
     constexpr int CB = 4 * C;                    // bytes per cell
     constexpr int kStageBytes = stage_bytes<C>();
@@ -987,15 +987,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                     dqz = (float)(g.dt * rr.dq[2]);
         const int YS = A.ys, ZS = A.zs, YZ = A.ys + A.zs, PY = A.py;
         const char* vb = (const char*)A.vol;
-        CellPair<C> p00, p10, p01, p11;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            p00.a[c] = p00.b[c] = p10.a[c] = p10.b[c] = 0.f;
-            p01.a[c] = p01.b[c] = p11.a[c] = p11.b[c] = 0.f;
-        }
         // the chunk's samples: the same positions, weights and order as
-        // in k_march_f32; a lane reloads its cells only when they change
-        auto step = [&](int n, auto&& load) {
+        // in k_march_f32; a lane reloads its cells P (the pairs at +0, +y,
+        // +z, +y+z) only when they change
+        auto step = [&](int n, CellPair<C> (&P)[4], auto&& load) {
             ++nsamp;
             const float fm = (float)(n - na);
             float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
@@ -1012,14 +1007,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 float t = acc[c];
-                t = fmaf(w000, p00.a[c], t);
-                t = fmaf(w100, p00.b[c], t);
-                t = fmaf(w010, p10.a[c], t);
-                t = fmaf(w110, p10.b[c], t);
-                t = fmaf(w001, p01.a[c], t);
-                t = fmaf(w101, p01.b[c], t);
-                t = fmaf(w011, p11.a[c], t);
-                t = fmaf(w111, p11.b[c], t);
+                t = fmaf(w000, P[0].a[c], t);
+                t = fmaf(w100, P[0].b[c], t);
+                t = fmaf(w010, P[1].a[c], t);
+                t = fmaf(w110, P[1].b[c], t);
+                t = fmaf(w001, P[2].a[c], t);
+                t = fmaf(w101, P[2].b[c], t);
+                t = fmaf(w011, P[3].a[c], t);
+                t = fmaf(w111, P[3].b[c], t);
                 acc[c] = t;
             }
         };
@@ -1027,39 +1022,48 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         bool gather = false;   // the rest of the range through the L1
         int c0 = na;
         while (c0 < nb) {
-            int c1 = min(nb, c0 + S);
-            // this lane's samples in the chunk, and the cells they read
-            const int s0 = max(c0, rr.n0), s1 = min(c1 - 1, rr.n1);
-            int lo0 = INT_MAX, lo1 = INT_MAX, lo2 = INT_MAX, hi0 = INT_MIN, hi1 = INT_MIN, hi2 = INT_MIN;
-            if (s0 <= s1) {
-                const float fa = (float)(s0 - na), fb = (float)(s1 - na);
-                const float xa = __builtin_amdgcn_fmed3f(fmaf(fa, dqx, q0x), 0.f, A.fn1[0]);
-                const float ya = __builtin_amdgcn_fmed3f(fmaf(fa, dqy, q0y), 0.f, A.fn1[1]);
-                const float za = __builtin_amdgcn_fmed3f(fmaf(fa, dqz, q0z), 0.f, A.fn1[2]);
-                const float xb = __builtin_amdgcn_fmed3f(fmaf(fb, dqx, q0x), 0.f, A.fn1[0]);
-                const float yb = __builtin_amdgcn_fmed3f(fmaf(fb, dqy, q0y), 0.f, A.fn1[1]);
-                const float zb = __builtin_amdgcn_fmed3f(fmaf(fb, dqz, q0z), 0.f, A.fn1[2]);
-                lo0 = (int)fminf(xa, xb);
-                lo1 = (int)fminf(ya, yb);
-                lo2 = (int)fminf(za, zb);
-                hi0 = (int)fmaxf(xa, xb) + 1;
-                hi1 = (int)fmaxf(ya, yb) + 1;
-                hi2 = (int)fmaxf(za, zb) + 1;
+            // the chunk [c0, c1) and the box of the cells its samples read;
+            // a box beyond the buffer is retried at half the length (in a
+            // loop of its own, so the chunk loop has a single way round)
+            int c1, lo0, lo1, lo2, hi0, hi1, hi2, dx, dy, dz, dxy, cells;
+            for (;;) {
+                c1 = min(nb, c0 + S);
+                // this lane's samples in the chunk, and the cells they read
+                const int s0 = max(c0, rr.n0), s1 = min(c1 - 1, rr.n1);
+                lo0 = lo1 = lo2 = INT_MAX;
+                hi0 = hi1 = hi2 = INT_MIN;
+                if (s0 <= s1) {
+                    const float fa = (float)(s0 - na), fb = (float)(s1 - na);
+                    const float xa = __builtin_amdgcn_fmed3f(fmaf(fa, dqx, q0x), 0.f, A.fn1[0]);
+                    const float ya = __builtin_amdgcn_fmed3f(fmaf(fa, dqy, q0y), 0.f, A.fn1[1]);
+                    const float za = __builtin_amdgcn_fmed3f(fmaf(fa, dqz, q0z), 0.f, A.fn1[2]);
+                    const float xb = __builtin_amdgcn_fmed3f(fmaf(fb, dqx, q0x), 0.f, A.fn1[0]);
+                    const float yb = __builtin_amdgcn_fmed3f(fmaf(fb, dqy, q0y), 0.f, A.fn1[1]);
+                    const float zb = __builtin_amdgcn_fmed3f(fmaf(fb, dqz, q0z), 0.f, A.fn1[2]);
+                    lo0 = (int)fminf(xa, xb);
+                    lo1 = (int)fminf(ya, yb);
+                    lo2 = (int)fminf(za, zb);
+                    hi0 = (int)fmaxf(xa, xb) + 1;
+                    hi1 = (int)fmaxf(ya, yb) + 1;
+                    hi2 = (int)fmaxf(za, zb) + 1;
+                }
+                lo0 = __ockl_wfred_min_i32(lo0);
+                lo1 = __ockl_wfred_min_i32(lo1);
+                lo2 = __ockl_wfred_min_i32(lo2);
+                hi0 = __ockl_wfred_max_i32(hi0);
+                hi1 = __ockl_wfred_max_i32(hi1);
+                hi2 = __ockl_wfred_max_i32(hi2);
+                if (lo0 > hi0) break;   // no lane samples this chunk
+                dx = hi0 - lo0 + 1;
+                dy = hi1 - lo1 + 1;
+                dz = hi2 - lo2 + 1;
+                dxy = dx * dy;
+                cells = dxy * dz;
+                if (cells <= BUF || S <= 4) break;
+                S >>= 1;
             }
-            lo0 = __ockl_wfred_min_i32(lo0);
-            lo1 = __ockl_wfred_min_i32(lo1);
-            lo2 = __ockl_wfred_min_i32(lo2);
-            hi0 = __ockl_wfred_max_i32(hi0);
-            hi1 = __ockl_wfred_max_i32(hi1);
-            hi2 = __ockl_wfred_max_i32(hi2);
-            if (lo0 > hi0) {        // no lane samples this chunk
+            if (lo0 > hi0) {
                 c0 = c1;
-                continue;
-            }
-            const int dx = hi0 - lo0 + 1, dy = hi1 - lo1 + 1, dz = hi2 - lo2 + 1;
-            const int dxy = dx * dy, cells = dxy * dz;
-            if (cells > BUF && S > 4) {
-                S >>= 1;             // retry a shorter chunk
                 continue;
             }
             if (cells > BUF) {
@@ -1096,34 +1100,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
+            // the cells live only within the chunk (no copies of them carried
+            // around the chunk loop) and need no initial value: every cell
+            // offset in the box is >= 0, so a lane's first sample loads
+            CellPair<C> P[4];
             int last = -1;
             const int s_lo = max(c0, rr.n0), s_hi = min(c1 - 1, rr.n1);
             const int base = (lo2 * dy + lo1) * dx + lo0;
             for (int n = s_lo; n <= s_hi; ++n)
-                step(n, [&](int ix, int iy, int iz) {
+                step(n, P, [&](int ix, int iy, int iz) {
                     const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
                     if (loc != last) {
                         last = loc;
-                        lds_pair<C>(st, loc, p00.a, p00.b);
-                        lds_pair<C>(st, loc + dx, p10.a, p10.b);
-                        lds_pair<C>(st, loc + dxy, p01.a, p01.b);
-                        lds_pair<C>(st, loc + dxy + dx, p11.a, p11.b);
+                        lds_pair<C>(st, loc, P[0].a, P[0].b);
+                        lds_pair<C>(st, loc + dx, P[1].a, P[1].b);
+                        lds_pair<C>(st, loc + dxy, P[2].a, P[2].b);
+                        lds_pair<C>(st, loc + dxy + dx, P[3].a, P[3].b);
                     }
                 });
             if (cells * 3 < BUF && S < 64) S <<= 1;
             c0 = c1;
         }
         if (gather) {
+            CellPair<C> P[4];   // offsets are >= 0: the first sample loads
             int last = -1;
             for (int n = max(c0, rr.n0); n <= min(nb - 1, rr.n1); ++n)
-                step(n, [&](int ix, int iy, int iz) {
+                step(n, P, [&](int ix, int iy, int iz) {
                     const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
                     if (voff != last) {
                         last = voff;
-                        p00 = load_pair_g<C>(vb, voff);
-                        p10 = load_pair_g<C>(vb, voff + YS);
-                        p01 = load_pair_g<C>(vb, voff + ZS);
-                        p11 = load_pair_g<C>(vb, voff + YZ);
+                        P[0] = load_pair_g<C>(vb, voff);
+                        P[1] = load_pair_g<C>(vb, voff + YS);
+                        P[2] = load_pair_g<C>(vb, voff + ZS);
+                        P[3] = load_pair_g<C>(vb, voff + YZ);
                     }
                 });
         }
