@@ -65,33 +65,54 @@ __device__ __forceinline__ T clampv(T x, T lo, T hi)
 __device__ __forceinline__ float clampv(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
 // ----------------------------------------------------------- reductions --
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
+// Sum over the 64 lanes of a wave with the device library's wave reduction
+// (a fixed DPP tree: the same order on every call, deterministic).
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
 
 // Block (256 threads = 4 waves) sum of NM doubles per thread; thread t < nm
-// writes dst[t * stride].  Fixed order: wave tree, then waves 0..3.
+// writes dst[t * stride].  Only waves 0 .. nw-1 hold data (the others add
+// nothing and skip their sums).  Fixed order: wave tree, then waves 0..nw-1.
 template <int NM>
-__device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double* dst, int stride)
+__device__ __forceinline__ void block_sum_store(double (&m)[NM], int nm, double* dst, int stride,
+                                                int nw = 4)
 {
     __shared__ double red[4][NM];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wv < nw) {
 #pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        double s = wave_sum(m[i]);
-        if (lane == 0) red[wv][i] = s;
+        for (int i = 0; i < NM; ++i) {
+            double s = wave_sum(m[i]);
+            if (lane == 0) red[wv][i] = s;
+        }
     }
     __syncthreads();
     if ((int)threadIdx.x < nm) {
         double s = red[0][threadIdx.x];
-        s += red[1][threadIdx.x];
-        s += red[2][threadIdx.x];
-        s += red[3][threadIdx.x];
+        for (int w2 = 1; w2 < nw; ++w2) s += red[w2][threadIdx.x];
         dst[(size_t)threadIdx.x * stride] = s;
     }
+}
+
+// The ray segments' sums (and sample counts) into segment 0's thread of
+// each ray (threads [0, rpb)); smem holds 256 (C + 1) words.  Afterwards
+// only segment 0 holds data: the block's moments need only its waves.
+template <int C>
+__device__ __forceinline__ void gather_segments(char* smem, int seg, int rpb, int sid, float (&acc)[C],
+                                                int& nsamp)
+{
+    float* segbuf = (float*)smem;
+    int* segn = (int*)(segbuf + 256 * C);
+#pragma unroll
+    for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
+    segn[threadIdx.x] = nsamp;
+    __syncthreads();
+    if (sid == 0)
+        for (int s2 = 1; s2 < seg; ++s2) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
+            nsamp += segn[threadIdx.x + s2 * rpb];
+        }
 }
 
 // Sum over the blocks of their partial sums, stored slot-major: part[m *
@@ -724,7 +745,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
     rr.n1 = -1;
     rr.dq[0] = rr.dq[1] = rr.dq[2] = 0.0;
     // LDS: first the block's ray set-ups, then the segments' partial sums
-    constexpr int kSmem = 256 * C * 4 > 128 * (int)sizeof(RayRange) ? 256 * C * 4 : 128 * (int)sizeof(RayRange);
+    constexpr int kSeg = 256 * (C + 1) * 4;   // gather_segments
+    constexpr int kSmem = kSeg > 128 * (int)sizeof(RayRange) ? kSeg : 128 * (int)sizeof(RayRange);
     __shared__ __align__(16) char smem[kSmem];
     if (A.ms.seg > 1) {
         // the segment-0 waves set up the block's rays, the others read them
@@ -822,16 +844,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             }
         }
     }
-    if (A.ms.seg > 1) {
-        float* segbuf = (float*)smem;
-#pragma unroll
-        for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
-        __syncthreads();
-        if (sid == 0)
-            for (int s2 = 1; s2 < A.ms.seg; ++s2)
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
-    }
+    if (A.ms.seg > 1) gather_segments<C>(smem, A.ms.seg, rpb, sid, acc, nsamp);
     if constexpr (H) {
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] *= A.ihs[c];   // exact: powers of two
@@ -845,7 +858,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         double mo[NM + 1];
 #pragma unroll
         for (int i = 0; i < NM; ++i) mo[i] = 0.0;
-        mo[NM] = (double)nsamp;
+        mo[NM] = sid == 0 ? (double)nsamp : 0.0;   // segments were gathered
         if (owner) {
             double yd = (double)A.y[iu + (size_t)g.nu * iv];
             double pd = (double)(dt * acc[0]);
@@ -864,7 +877,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 }
             }
         }
-        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x);
+        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x, rpb / 64);
     }
 }
 
@@ -951,7 +964,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
     // LDS: the block's ray set-ups, then the waves' staging buffers, then
     // the segments' partial sums (one after the other, so they share it)
     constexpr int kStage = 4 * kStageBytes;
-    constexpr int kRest = 256 * C * 4 > 128 * (int)sizeof(RayRange) ? 256 * C * 4 : 128 * (int)sizeof(RayRange);
+    constexpr int kSeg = 256 * (C + 1) * 4;   // gather_segments
+    constexpr int kRest = kSeg > 128 * (int)sizeof(RayRange) ? kSeg : 128 * (int)sizeof(RayRange);
     constexpr int kSmem = kStage > kRest ? kStage : kRest;
     __shared__ __align__(16) char smem[kSmem];
     if (A.ms.seg > 1) {
@@ -1139,14 +1153,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
     }
     if (A.ms.seg > 1) {
         __syncthreads();   // every wave is done with its staging buffer
-        float* segbuf = (float*)smem;
-#pragma unroll
-        for (int c = 0; c < C; ++c) segbuf[threadIdx.x * C + c] = acc[c];
-        __syncthreads();
-        if (sid == 0)
-            for (int s2 = 1; s2 < A.ms.seg; ++s2)
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[c] += segbuf[(threadIdx.x + s2 * rpb) * C + c];
+        gather_segments<C>(smem, A.ms.seg, rpb, sid, acc, nsamp);
     }
     const bool owner = valid && sid == 0;
     const float dt = (float)g.dt;
@@ -1156,7 +1163,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         double mo[NM + 1];
 #pragma unroll
         for (int i = 0; i < NM; ++i) mo[i] = 0.0;
-        mo[NM] = (double)nsamp;
+        mo[NM] = sid == 0 ? (double)nsamp : 0.0;   // segments were gathered
         if (owner) {
             double yd = (double)A.y[iu + (size_t)g.nu * iv];
             double pd = (double)(dt * acc[0]);
@@ -1175,7 +1182,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 }
             }
         }
-        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x);
+        block_sum_store<NM + 1>(mo, NM + 1, A.partials + blockIdx.x, (int)gridDim.x, rpb / 64);
     }
 }
 
