@@ -76,6 +76,23 @@ pcr_status check_march_image(const pcr_grid& g, int C, pcr_dtype compute)
     return PCR_OK;
 }
 
+// The FP32 march indexes a ray's samples from its segment start with an FP32
+// counter, exact below 2^24: the longest possible path through the padded
+// grid must hold fewer samples than that.
+pcr_status check_march_steps(const pcr_grid& g, const pcr_geom& G, pcr_dtype compute)
+{
+    if (compute != PCR_F32) return PCR_OK;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = (g.n[a] + 3.0) * g.spacing_mm[a];
+        d2 += e * e;
+    }
+    if (std::sqrt(d2) / G.step_mm >= 16777216.0)
+        return fail(PCR_EINVAL, "step_mm %.3g too small for the FP32 march: a ray through the grid would "
+                                "take 2^24 samples or more", G.step_mm);
+    return PCR_OK;
+}
+
 pcr_status check_geom(const pcr_geom* G)
 {
     if (!G) return fail(PCR_EINVAL, "geometry is NULL");
@@ -288,6 +305,7 @@ static void flush_locked()
 pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
 {
     PCR_TRY(check_march_image(*grid, mode_ == PCR_GRAD_FUSED ? channels_for(model->K + 1) : 1, compute));
+    PCR_TRY(check_march_steps(*grid, G, compute));
     y = y_;
     mode = mode_;
     rg = make_ray_geom(*grid, G);
@@ -794,6 +812,7 @@ pcr_status pcr_forward_project(const pcr_grid* grid, const pcr_geom* geom, pcr_d
     PCR_TRY(check_compute(compute));
     if (!vol_dev || !proj_dev) return fail(PCR_EINVAL, "NULL device pointer");
     PCR_TRY(check_march_image(*grid, 1, compute));
+    PCR_TRY(check_march_steps(*grid, *geom, compute));
     hipStream_t s = (hipStream_t)stream;
     int dev;
     PCR_TRY(current_device(&dev));
@@ -824,6 +843,7 @@ pcr_status pcr_forward_project_noalloc(const pcr_grid* grid, const pcr_geom* geo
     PCR_TRY(check_compute(compute));
     if (!vol_dev || !proj_dev) return fail(PCR_EINVAL, "NULL device pointer");
     PCR_TRY(check_march_image(*grid, 1, compute));
+    PCR_TRY(check_march_steps(*grid, *geom, compute));
     PadLayout L = make_pad(*grid, 1);
     const size_t bytes = L.cells() * dtype_size(compute);
     if (bytes > PCR_NOALLOC_SCRATCH_BYTES)

@@ -57,6 +57,7 @@ pcr_status check_geom(const pcr_geom* G);
 // PCR_EINVAL unless the FP32 march can address an image of C channels per
 // cell on this grid in both in-plane axis orders (see march_f32_fits).
 pcr_status check_march_image(const pcr_grid& g, int C, pcr_dtype compute);
+pcr_status check_march_steps(const pcr_grid& g, const pcr_geom& G, pcr_dtype compute);
 pcr_status check_compute(pcr_dtype d);
 pcr_status check_storage(pcr_dtype d);
 pcr_status check_model(const pcr_model* m);

@@ -1004,9 +1004,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         // the chunk's samples: the same positions, weights and order as
         // in k_march_f32; a lane reloads its cells P (the pairs at +0, +y,
         // +z, +y+z) only when they change
-        auto step = [&](int n, CellPair<C> (&P)[4], auto&& load) {
-            ++nsamp;
-            const float fm = (float)(n - na);
+        // (fm: the sample's index relative to na, as a float)
+        auto step = [&](float fm, CellPair<C> (&P)[4], auto&& load) {
             float qx = __builtin_amdgcn_fmed3f(fmaf(fm, dqx, q0x), 0.f, A.fn1[0]);
             float qy = __builtin_amdgcn_fmed3f(fmaf(fm, dqy, q0y), 0.f, A.fn1[1]);
             float qz = __builtin_amdgcn_fmed3f(fmaf(fm, dqz, q0z), 0.f, A.fn1[2]);
@@ -1121,8 +1120,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             int last = -1;
             const int s_lo = max(c0, rr.n0), s_hi = min(c1 - 1, rr.n1);
             const int base = (lo2 * dy + lo1) * dx + lo0;
-            for (int n = s_lo; n <= s_hi; ++n)
-                step(n, P, [&](int ix, int iy, int iz) {
+            // the samples, counted once per chunk; the index runs as a float
+            // beside the integer count (|n - na| < 2^24: exact)
+            const int cnt = s_hi - s_lo + 1;
+            if (cnt > 0) nsamp += cnt;
+            float fm = (float)(s_lo - na);
+            for (int i = 0; i < cnt; ++i, fm += 1.0f)
+                step(fm, P, [&](int ix, int iy, int iz) {
                     const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
                     if (loc != last) {
                         last = loc;
@@ -1138,8 +1142,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         if (gather) {
             CellPair<C> P[4];   // offsets are >= 0: the first sample loads
             int last = -1;
-            for (int n = max(c0, rr.n0); n <= min(nb - 1, rr.n1); ++n)
-                step(n, P, [&](int ix, int iy, int iz) {
+            const int g0 = max(c0, rr.n0), cnt = min(nb - 1, rr.n1) - g0 + 1;
+            if (cnt > 0) nsamp += cnt;
+            float fm = (float)(g0 - na);
+            for (int i = 0; i < cnt; ++i, fm += 1.0f)
+                step(fm, P, [&](int ix, int iy, int iz) {
                     const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
                     if (voff != last) {
                         last = voff;

@@ -193,3 +193,23 @@ def test_noalloc_projection_refuses_oversized_grid_before_any_launch():
     g = _fake_grid((256, 256, 128))
     st = L.pcr_forward_project_noalloc(C.byref(g), C.byref(G), _lib.PCR_F64, fake, fake, None)
     assert st == _lib.PCR_EINVAL and b"fixed scratch" in L.pcr_last_error()
+
+
+def test_march_step_limit_is_rejected_before_any_launch():
+    """The FP32 march counts a ray's samples with an FP32 index, exact below
+    2^24: a step so small that a ray through the grid would take 2^24
+    samples or more is refused with PCR_EINVAL by validation, before the
+    library touches a device (this runs without a GPU)."""
+    import ctypes as C
+    from paper_1004_0014_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpcr.so not built")
+    L = _lib.lib()
+    fake = C.c_void_p(0x10000)
+    g = _fake_grid((64, 64, 32))
+    G = _fake_geom()
+    G.step_mm = 1e-6      # a ~90 mm diagonal in 9e7 samples
+    for fn in (L.pcr_forward_project, L.pcr_forward_project_noalloc):
+        st = fn(C.byref(g), C.byref(G), _lib.PCR_F32, fake, fake, None)
+        assert st == _lib.PCR_EINVAL
+        assert b"too small for the FP32 march" in L.pcr_last_error()
