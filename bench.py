@@ -190,12 +190,14 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
     lat, iters, trials, werr, terr, evals, samples, ends, ws = [], [], [], [], [], [], [], [], []
     w = list(w0)
     hist = [] if hist is None else hist
+    # each frame's time stamp arrives with the frame; the truth used to score
+    # the results is looked up after the timed loop
+    times = [W.frame(i)[1] for i in idxs]
     torch.cuda.synchronize()
     if profile:
         _lib.profile_enable(True, profile_kinds)
     t_start = time.perf_counter()
-    for n, (y, G, i) in enumerate(zip(ys, geoms, idxs)):
-        t_i = W.frame(i)[1]
+    for n, (y, G, i, t_i) in enumerate(zip(ys, geoms, idxs, times)):
         t0 = time.perf_counter()
         if predict_order > 0 and len(hist) >= 2:
             last = hist[-(predict_order + 1):]
@@ -220,11 +222,12 @@ def run_sequence(ctx, W, ys, geoms, idxs, opts, w0, profile=False, predict_order
         # how the solve ended: tolerance met, iteration cap, line search exhausted
         ends.append("tol" if st["status"] == 0 else
                     ("cap" if st["iterations"] >= opts.max_iter else "armijo"))
-        _, _, phi, wt = W.frame(i)
-        werr.append(float(np.linalg.norm(np.array(w) - wt) / np.linalg.norm(wt)))
         terr.append(st["tumor_mm"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    for wi, i in zip(ws, idxs):
+        wt = W.frame(i)[3]
+        werr.append(float(np.linalg.norm(np.array(wi) - wt) / np.linalg.norm(wt)))
     prof = _lib.profile_read() if profile else None
     if profile:
         _lib.profile_enable(False)

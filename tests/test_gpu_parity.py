@@ -77,6 +77,49 @@ def test_backproject_parity_and_adjoint(n, sp, nu, nv, du, step, ang, dtype):
     assert abs(lhs - rhs) <= tol * np.sum(np.abs(px) * np.abs(r))
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_coarse_detector_and_long_steps(dtype):
+    """Geometries off the usual path of the staged march and of the column
+    backprojection: a coarse detector (neighbouring rays ~15 voxels apart, so
+    a wave's cells for even 4 samples overflow its LDS stage and the march
+    gathers the rest through the L1) and a step of 2.5 voxels (a ray moves
+    more than one voxel per sample).  Projection, backprojection with the
+    adjoint identity, and the fused cost and gradient follow the oracle."""
+    L = _lib()
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    g = S.Grid((48, 40, 32), (2.0, 2.0, 2.0))
+    f_t, f = rounded(S.phantom(g, seed=8), tdt)
+    for G in (S.Geom(math.radians(35.0), 12, 10, 25.0, 25.0, 1.0, off_u=3.0),
+              S.Geom(math.radians(160.0), 64, 48, 3.0, 3.0, 5.0, off_v=-1.0)):
+        p = L.forward_project(g, G, f_t.to(DEV)).cpu().numpy()
+        po = oracle.project(g, G, f)
+        assert rel_l2(p, po) <= tol, G.du
+        r_t, r = rounded(S.seeded(9, (G.nv, G.nu)), tdt)
+        bp = L.backproject_residual(g, G, r_t.to(DEV)).cpu().numpy()
+        assert rel_l2(bp, oracle.backproject(g, G, r)) <= tol, G.du
+        pr = L.forward_project(g, G, f_t.to(DEV)).cpu().double().numpy()
+        assert abs(np.vdot(pr, r) - np.vdot(f, bp)) <= tol * np.sum(np.abs(pr) * np.abs(r)), G.du
+    if dtype == "f64":
+        return
+    # the fused path (4- and 8-channel images) on the coarse detector
+    for K in (3, 5):
+        mean, U = _smooth_model(g, K, seed=30 + K)
+        mean_t, mean = rounded(mean, torch.float32)
+        U_t, U = rounded(U, torch.float32)
+        ctx = L.Context(g, L.DeviceModel(mean_t.to(DEV), U_t.to(DEV)), f_t.to(DEV))
+        w_true = np.random.default_rng(40 + K).uniform(-2.0, 2.0, K)
+        G = S.Geom(math.radians(35.0), 12, 10, 25.0, 25.0, 1.0, off_u=3.0)
+        y_np = oracle.project(g, G, oracle.warp(g, f, oracle.compose(g, mean, U, w_true)))
+        y = torch.tensor(y_np, dtype=torch.float32, device=DEV)
+        y_np = y.double().cpu().numpy()
+        J, grad = ctx.cost_grad(y, G, 0.5 * w_true, 0.9, 0.01)
+        Jo, go = oracle.cost_grad(g, G, f, mean, U, 0.5 * w_true, y_np, 0.9, 0.01)
+        assert abs(J - Jo) <= 2e-5 * Jo, K
+        assert rel_l2(grad, go) <= 1e-4, K
+        ctx.close()
+
+
 def test_ray_missing_volume_and_tiny_detector():
     L = _lib()
     g = S.Grid((8, 8, 8), (1.0, 1.0, 1.0))
