@@ -902,12 +902,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 template <int C>
 constexpr int stage_bytes() { return C <= 4 ? 6144 : 9216; }
 
-// Cells `cell` and `cell` + 1 of a staging buffer of C-float cells.
+// a * b + c with a, b < 2^24 in one v_mad_u32_u24 (b wave-uniform; left to
+// itself the compiler spreads a two-term cell offset over more instructions)
+__device__ __forceinline__ unsigned mad_u24(int a, unsigned b, unsigned c)
+{
+    unsigned d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+
+// floor(x / d) for 0 <= x < 2^21 and d >= 1, given rd = rcp(d) from the
+// hardware reciprocal (within 1 ulp): (x + 0.5) rd is within 2^-22 relative
+// of (x + 0.5) / d, less than 0.5 / d absolute, and (x + 0.5) / d lies at
+// least 0.5 / d from every integer, so truncation gives the exact quotient.
+__device__ __forceinline__ int small_quot(int x, float rd)
+{
+    return (int)(((float)x + 0.5f) * rd);
+}
+
+// The cells at byte offset `off` of a staging buffer of C-float cells and
+// the cell after it.
 template <int C>
-__device__ __forceinline__ void lds_pair(const float* st, int cell, float (&a)[C], float (&b)[C])
+__device__ __forceinline__ void lds_pair(const char* st, unsigned off, float (&a)[C], float (&b)[C])
 {
     if constexpr (C % 4 == 0) {
-        const float4* q = (const float4*)(st + cell * C);
+        const float4* q = (const float4*)(st + off);
 #pragma unroll
         for (int h = 0; h < C / 4; ++h) {
             const float4 u = q[h], v = q[C / 4 + h];
@@ -915,11 +934,12 @@ __device__ __forceinline__ void lds_pair(const float* st, int cell, float (&a)[C
             b[4 * h] = v.x; b[4 * h + 1] = v.y; b[4 * h + 2] = v.z; b[4 * h + 3] = v.w;
         }
     } else if constexpr (C == 2) {
-        const float2 u = *(const float2*)(st + cell * 2), v = *(const float2*)(st + cell * 2 + 2);
+        const float2 u = *(const float2*)(st + off), v = *(const float2*)(st + off + 8);
         a[0] = u.x; a[1] = u.y; b[0] = v.x; b[1] = v.y;
     } else {
-        a[0] = st[cell];
-        b[0] = st[cell + 1];
+        const float* q = (const float*)(st + off);
+        a[0] = q[0];
+        b[0] = q[1];
     }
 }
 
@@ -1091,23 +1111,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 // cell e = row dx + lx, row = lz dy + ly: each lane starts at
-                // e = lane and advances by 64 cells (64 / dx rows and 64 % dx
-                // cells); quotients from rounded reciprocals, then corrected
-                // (off by at most one)
-                const float idx_ = 1.0f / (float)dx, idy_ = 1.0f / (float)dy;
-                const int srow = 64 / dx, sx = 64 - srow * dx;
-                int row = (int)(((float)lane + 0.5f) * idx_);
+                // e = lane and advances by 64 cells, i.e. by sz slices, sy
+                // rows and sx cells with at most one carry into the row and
+                // one into the slice; its image offset follows the same
+                // carries (unsigned: the offset one step past the box may
+                // wrap, but every offset loaded is that of a box cell)
+                const float rdx = __builtin_amdgcn_rcpf((float)dx), rdy = __builtin_amdgcn_rcpf((float)dy);
+                const int row = small_quot(lane, rdx);
                 int lx = lane - row * dx;
-                if (lx < 0) { --row; lx += dx; } else if (lx >= dx) { ++row; lx -= dx; }
+                const int lz = small_quot(row, rdy);
+                int ly = row - lz * dy;
+                const int srow = __builtin_amdgcn_readfirstlane(small_quot(64, rdx));
+                const int sz = __builtin_amdgcn_readfirstlane(small_quot(srow, rdy));
+                const int sx = 64 - srow * dx, sy = srow - sz * dy;
+                const unsigned uYS = (unsigned)YS, uZS = (unsigned)ZS;
+                const unsigned a0 = (unsigned)(sx * CB) + (unsigned)sy * uYS + (unsigned)sz * uZS;
+                const unsigned a1 = uYS - (unsigned)(dx * CB), a2 = uZS - (unsigned)dy * uYS;
+                unsigned goff = (unsigned)((lo0 + lx) * CB) + __umul24(__umul24(lo2 + lz, PY) + lo1 + ly, YS);
                 for (int e = lane; e < cells; e += 64) {
-                    int lz = (int)(((float)row + 0.5f) * idy_);
-                    int ly = row - lz * dy;
-                    if (ly < 0) { --lz; ly += dy; } else if (ly >= dy) { ++lz; ly -= dy; }
-                    const int goff = (lo0 + lx) * CB + (int)__umul24(__umul24(lo2 + lz, PY) + lo1 + ly, YS);
                     stage_cell<C>(vb + goff, st + e * C);
                     lx += sx;
-                    row += srow;
-                    if (lx >= dx) { lx -= dx; ++row; }
+                    const bool carry_x = lx >= dx;
+                    lx -= carry_x ? dx : 0;
+                    ly += sy + (carry_x ? 1 : 0);
+                    const bool carry_y = ly >= dy;
+                    ly -= carry_y ? dy : 0;
+                    goff += a0 + (carry_x ? a1 : 0u) + (carry_y ? a2 : 0u);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
@@ -1116,24 +1145,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             // the cells live only within the chunk (no copies of them carried
             // around the chunk loop) and need no initial value: every cell
             // offset in the box is >= 0, so a lane's first sample loads
+            // (the box cell of padded cell (ix, iy, iz) at byte offset
+            // iz cz + iy cy + ix CB - (lo2 cz + lo1 cy + lo0 CB), in unsigned
+            // arithmetic: the wrap of the products cancels in the difference)
             CellPair<C> P[4];
-            int last = -1;
+            unsigned last = ~0u;
             const int s_lo = max(c0, rr.n0), s_hi = min(c1 - 1, rr.n1);
-            const int base = (lo2 * dy + lo1) * dx + lo0;
-            // the samples, counted once per chunk; the index runs as a float
-            // beside the integer count (|n - na| < 2^24: exact)
+            const unsigned cy = (unsigned)(dx * CB), cz = (unsigned)(dxy * CB);
+            // (offsets from the start of the block's LDS: the wave's buffer
+            // starts kStageBytes x wave into it)
+            const unsigned base = (unsigned)lo2 * cz + (unsigned)lo1 * cy + (unsigned)(lo0 * CB) -
+                                  (unsigned)__builtin_amdgcn_readfirstlane(wave * kStageBytes);
+            const char* stb = smem;
+            // the samples, counted once per chunk; the loop runs on the
+            // index as a float (0 <= n - na < 2^24: exact)
             const int cnt = s_hi - s_lo + 1;
             if (cnt > 0) nsamp += cnt;
-            float fm = (float)(s_lo - na);
-            for (int i = 0; i < cnt; ++i, fm += 1.0f)
+            const float fe = (float)(s_hi - na);
+            for (float fm = (float)(s_lo - na); fm <= fe; fm += 1.0f)
                 step(fm, P, [&](int ix, int iy, int iz) {
-                    const int loc = (int)__umul24(iz, dxy) + (int)__umul24(iy, dx) + ix - base;
+                    const unsigned loc = mad_u24(iz, cz, mad_u24(iy, cy, (unsigned)(ix * CB) - base));
                     if (loc != last) {
                         last = loc;
-                        lds_pair<C>(st, loc, P[0].a, P[0].b);
-                        lds_pair<C>(st, loc + dx, P[1].a, P[1].b);
-                        lds_pair<C>(st, loc + dxy, P[2].a, P[2].b);
-                        lds_pair<C>(st, loc + dxy + dx, P[3].a, P[3].b);
+                        lds_pair<C>(stb, loc, P[0].a, P[0].b);
+                        lds_pair<C>(stb, loc + cy, P[1].a, P[1].b);
+                        lds_pair<C>(stb, loc + cz, P[2].a, P[2].b);
+                        lds_pair<C>(stb, loc + cz + cy, P[3].a, P[3].b);
                     }
                 });
             if (cells * 3 < BUF && S < 64) S <<= 1;
@@ -1142,10 +1179,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
         if (gather) {
             CellPair<C> P[4];   // offsets are >= 0: the first sample loads
             int last = -1;
-            const int g0 = max(c0, rr.n0), cnt = min(nb - 1, rr.n1) - g0 + 1;
-            if (cnt > 0) nsamp += cnt;
-            float fm = (float)(g0 - na);
-            for (int i = 0; i < cnt; ++i, fm += 1.0f)
+            const int g0 = max(c0, rr.n0), g1 = min(nb - 1, rr.n1);
+            if (g1 >= g0) nsamp += g1 - g0 + 1;
+            const float fe = (float)(g1 - na);
+            for (float fm = (float)(g0 - na); fm <= fe; fm += 1.0f)
                 step(fm, P, [&](int ix, int iy, int iz) {
                     const int voff = ix * CB + (int)__umul24(__umul24(iz, PY) + iy, YS);
                     if (voff != last) {
