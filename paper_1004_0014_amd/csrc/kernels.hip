@@ -957,9 +957,14 @@ __device__ __forceinline__ void stage_cell(const char* src, float* dst)
     }
 }
 
-template <int C>
+// KC: the channels whose sums are used (A.kc: the moments and the projection
+// read only those; the others stay zero); the sample loop accumulates only
+// these, so a 5- or 6-channel image stored in 8-channel cells (K = 4, 5)
+// does not pay for the channels it does not use.
+template <int C, int KC = C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 6 : 4))) k_march_lds(MarchArgs A)
 {
+    static_assert(KC >= 1 && KC <= C, "used channels");
     constexpr int CB = 4 * C;                    // bytes per cell
     constexpr int kStageBytes = stage_bytes<C>();
     constexpr int BUF = kStageBytes / CB;        // cells per wave
@@ -1038,7 +1043,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
             const float w000 = bx * w00, w100 = ax * w00, w010 = bx * w10, w110 = ax * w10;
             const float w001 = bx * w01, w101 = ax * w01, w011 = bx * w11, w111 = ax * w11;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
+            for (int c = 0; c < KC; ++c) {
                 float t = acc[c];
                 t = fmaf(w000, P[0].a[c], t);
                 t = fmaf(w100, P[0].b[c], t);
@@ -2100,7 +2105,18 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
         case 1: k_march_lds<1><<<blocks, 256, 0, s>>>(A); break;
         case 2: k_march_f32<2, false><<<blocks, 256, 0, s>>>(A); break;
         case 4: k_march_lds<4><<<blocks, 256, 0, s>>>(A); break;
-        case 8: k_march_lds<8><<<blocks, 256, 0, s>>>(A); break;
+        case 8:
+            // K = 4 and 5 use 5 and 6 of the 8 channels: the loads of the
+            // unused ones narrow to one or two dwords.  (Three of four, the
+            // 12-byte LDS reads of K = 2 in 4-channel cells or K = 6 in
+            // 8-channel ones, were slower than summing the zero channel:
+            // 183.6 against 145.6 us at K = 2.)
+            switch (kc) {
+            case 5: k_march_lds<8, 5><<<blocks, 256, 0, s>>>(A); break;
+            case 6: k_march_lds<8, 6><<<blocks, 256, 0, s>>>(A); break;
+            default: k_march_lds<8><<<blocks, 256, 0, s>>>(A); break;
+            }
+            break;
         default: return hipErrorInvalidValue;
         }
     }
