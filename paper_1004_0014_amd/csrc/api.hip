@@ -334,9 +334,11 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
         PCR_TRY(sc->volc.ensure(std::max(need, sc->volc_floor), dev, s));
         if (fresh || !sc->volc_zeroed || !sc->volc_layout.same_storage(sc->Lc)) {
             // border cells of one layout (grid, channel count, element
-            // type, axis order) are interior cells of another
+            // type, axis order) are interior cells of another; only this
+            // layout's cells are read (a serving slot's buffer is sized for
+            // its largest stream)
             PROF(ZERO, s);
-            HIP_TRY(launch_zero(sc->volc.p, sc->volc.bytes, s));
+            HIP_TRY(launch_zero(sc->volc.p, need, s));
             sc->volc_layout = sc->Lc;
             sc->volc_zeroed = true;
         }
