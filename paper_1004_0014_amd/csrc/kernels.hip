@@ -329,9 +329,20 @@ __global__ void __launch_bounds__(256) k_warp_fused(const F* __restrict__ f0,
         store_cell<R, C, H>(o, hs);
 }
 
-// y-fastest padded layout: a 128 x 8 (x, y) tile per block, computed with
-// x-contiguous reads (512-byte runs of each field), staged in LDS and written
-// as 8-cell runs along y.
+// Width (x) of the y-fastest warp's tiles: the widest of 128, 64 or 32
+// voxels whose 8-row tile of cells stays within about 8 KB of LDS, so that a
+// block still finds room on a CU whose LDS the march's staging mostly holds
+// (a serving engine runs both at once).
+template <typename R, int C, bool H>
+constexpr int yf_tile_x()
+{
+    constexpr int cb = (int)sizeof(CellOf<R, C, H>);
+    return 8 * 128 * cb <= 8448 ? 128 : (8 * 64 * cb <= 8448 ? 64 : 32);
+}
+
+// y-fastest padded layout: a TX x 8 (x, y) tile per block, computed with
+// x-contiguous reads (4 TX-byte runs of each field), staged in LDS and
+// written as 8-cell runs along y.
 template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        const S* __restrict__ mean,
@@ -341,24 +352,25 @@ __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
                                                        int gx, int gy,
                                                        CellOf<R, C, H>* __restrict__ out)
 {
-    __shared__ CellOf<R, C, H> tile[8][129];
+    constexpr int TX = yf_tile_x<R, C, H>();
+    __shared__ CellOf<R, C, H> tile[8][TX + 1];
     // tiles in XCD order: each XCD's L2 sees a contiguous band of tile rows,
     // so the f0 taps that neighbouring tiles share (displacements reach
     // several voxels) are fetched into one L2 (-7 % at 80-90 deg)
     const int lb = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = lb % gx, rb = lb / gx;
-    const int i0 = b.lo[0] + bx * 128, j0 = b.lo[1] + (rb % gy) * 8, k = b.lo[2] + rb / gy;
+    const int i0 = b.lo[0] + bx * TX, j0 = b.lo[1] + (rb % gy) * 8, k = b.lo[2] + rb / gy;
     const int t = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int il = t & 127, jl = (t >> 7) + 2 * r;
+    for (int r = 0; r < TX / 32; ++r) {
+        const int il = t % TX, jl = t / TX + (256 / TX) * r;
         const int i = i0 + il, j = j0 + jl;
         if (i < b.hi[0] && j < b.hi[1])
             tile[jl][il] = store_cell<R, C, H>(warp_cell<R, S, F, C, TAN>(f0, mean, U, K, w, g, i, j, k), hs);
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < TX / 32; ++r) {
         const int jl = t & 7, il = (t >> 3) + 32 * r;
         const int i = i0 + il, j = j0 + jl;
         if (i < b.hi[0] && j < b.hi[1])
@@ -1942,16 +1954,18 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
     const int ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
     dim3 grid((ex + 255) / 256, ey, ez), blk(256, 1);
     auto w = wvec(w_eff, K);
-    // one-dimensional grid (the kernel orders its tiles by XCD)
-    const int gxy = (ex + 127) / 128, gyy = (ey + 7) / 8;
-    if ((long)gxy * gyy * ez > 0x7fffffffL) return hipErrorInvalidValue;
-    dim3 grid_yf((unsigned)((long)gxy * gyy * ez));
+    // one-dimensional grid (the kernel orders its tiles by XCD), tiles of
+    // yf_tile_x x 8 voxels
+    const int gyy = (ey + 7) / 8;
+    auto grid_yf = [&](int tx) { return dim3((unsigned)((long)((ex + tx - 1) / tx) * gyy * ez)); };
+    if ((long)((ex + 31) / 32) * gyy * ez > 0x7fffffffL) return hipErrorInvalidValue;
     Chan<float, 8> hs;
     for (int c = 0; c < 8; ++c) hs.v[c] = L.hs[c];
 #define PCR_WF2(C, T, H)                                                                          \
-    (L.yfast ? k_warp_fused_yf<R, S, F, C, T, H><<<grid_yf, 256, 0, s>>>(                         \
+    (L.yfast ? k_warp_fused_yf<R, S, F, C, T, H><<<grid_yf(yf_tile_x<R, C, H>()), 256, 0, s>>>(  \
                    (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs, b,    \
-                   gxy, gyy, (CellOf<R, C, H>*)padded)                                            \
+                   (ex + yf_tile_x<R, C, H>() - 1) / yf_tile_x<R, C, H>(), gyy,                   \
+                   (CellOf<R, C, H>*)padded)                                                      \
              : k_warp_fused<R, S, F, C, T, H><<<grid, blk, 0, s>>>(                               \
                    (const F*)f0, (const S*)mean, (const S*)U, K, w, vox(g), L.px, L.py, hs, b,    \
                    (CellOf<R, C, H>*)padded))
