@@ -260,9 +260,10 @@ def _smooth_model(g, K, seed):
     return mean, U
 
 
-@pytest.mark.parametrize("K", [1, 5, 7])
+@pytest.mark.parametrize("K", [1, 2, 4, 5, 6, 7])
 def test_cost_grad_channel_counts(K):
-    """Fused images of 2 and 8 channels (K = 1, 5, 7) on a ragged grid, on
+    """Fused images of 2, 4 and 8 channels (K = 1, 2, 4, 5, 6, 7: every
+    channel count the march sums, from 2 of 2 to 8 of 8) on a ragged grid, on
     both layouts: J and the gradient follow the oracle, and so does a short
     solve."""
     L = _lib()
