@@ -285,7 +285,18 @@ def test_cost_grad_channel_counts(K):
         J, grad = ctx.cost_grad(y, G, w, 0.9, 0.01)
         Jo, go = oracle.cost_grad(g, G, f0, mean, U, w, y_np, 0.9, 0.01)
         assert abs(J - Jo) <= 2e-5 * Jo, (K, ang)
-        assert rel_l2(grad, go) <= 1e-4, (K, ang)
+        # The tangents use the derivative of the interpolant in the floor cell
+        # of the warp position (its right derivative, which jumps across cell
+        # faces).  The kernels place a voxel in its cell from FP32 positions,
+        # the oracle from FP64 ones; a voxel within FP32 rounding of a face
+        # (two of them at K = 4 here) takes the neighbouring cell's derivative,
+        # which on this small grid moves the gradient by up to ~2e-4.  So the
+        # bound against the oracle is 5e-4, and the two gradient paths (fused
+        # tangent moments; backprojection and contraction), which share those
+        # FP32 positions, must agree with each other to 1e-5.
+        assert rel_l2(grad, go) <= 5e-4, (K, ang)
+        _, grad_adj = ctx.cost_grad(y, G, w, 0.9, 0.01, mode=L.GRAD_ADJOINT)
+        assert rel_l2(grad, grad_adj) <= 1e-5, (K, ang)
         ws, ab, st = ctx.reconstruct(y, G, np.zeros(K), L.default_opts(max_iter=8, step0=1.0))
         wo, abo, sto, _ = oracle.solve(g, G, f0, mean, U, y_np, np.zeros(K),
                                        oracle.SolveOpts(max_iter=8, step0=1.0))
