@@ -49,7 +49,7 @@
  *     image, (nx+3)(ny+3)(nz+3) cells of C FP32 channels, with 32-bit byte
  *     offsets.  That image must stay below 2 GiB (with padded rows below
  *     16 MiB and (ny+3)(nz+3), (nx+3)(nz+3) below 2^24 cells).  C = 1 for
- *     pcr_forward_project; C = K + 1 rounded up to 2, 4 or 8 for contexts and
+ *     pcr_forward_project; C = K + 1 rounded up to 2, 4, 6 or 8 for contexts and
  *     server streams.  A larger grid returns PCR_EINVAL from
  *     pcr_forward_project, pcr_ctx_create, pcr_cost_grad,
  *     pcr_reconstruct_from_projection and pcr_server_add_stream before any

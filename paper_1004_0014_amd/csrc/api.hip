@@ -320,6 +320,7 @@ pcr_status Evaluator::prepare(const void* y_, const pcr_geom& G, int mode_)
     // FP32 arithmetic and FP64 moments; the channel scales need the bounds
     // the support pass records
     if (image_f16 && compute == PCR_F32 && sup && sup->valid) {
+        sc->Lc = make_pad(*grid, channels_for_half(model->K + 1), yfast);
         sc->Lc.half = true;
         half_scales(*sup, *grid, model->K, sc->Lc.hs);
     }

@@ -69,7 +69,11 @@ inline void effective_w(const pcr_model& m, const double* w, double* w_eff)
     for (int k = 0; k < m.K; ++k) w_eff[k] = w[k] * (m.scale ? m.scale[k] : 1.0);
 }
 
-inline int channels_for(int kc) { return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8; }
+// Channels per cell of an image with kc channels in use: 1, 2, 4, 6 or 8
+// (6: 24-byte FP32 cells for K = 4 and 5).  FP16 cells take 4 or 8 channels
+// (their loads read 8 halves at a time), so 5 or 6 in use take 8 there.
+inline int channels_for(int kc) { return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : kc <= 6 ? 6 : 8; }
+inline int channels_for_half(int kc) { return kc <= 2 ? 2 : kc <= 4 ? 4 : 8; }
 
 // Device bytes of a model and reference image stored as given.
 inline size_t model_bytes(const pcr_grid& g, int K, pcr_dtype storage, pcr_dtype f0_dtype)

@@ -52,8 +52,11 @@ template <> __device__ __forceinline__ double widen<double, bf16>(bf16 v)
 template <> __device__ __forceinline__ float widen<float, _Float16>(_Float16 v) { return (float)v; }
 template <> __device__ __forceinline__ double widen<double, _Float16>(_Float16 v) { return (double)(float)v; }
 
+// C channels of type R, aligned to the largest power of two (at most 16
+// bytes) that divides their size, so that arrays of cells have no padding
+// (6 FP32 channels: 24-byte cells at 8-byte alignment).
 template <typename R, int C>
-struct alignas((sizeof(R) * C) >= 16 ? 16 : (sizeof(R) * C)) Chan {
+struct alignas(((sizeof(R) * C) & (0 - sizeof(R) * C)) >= 16 ? 16 : ((sizeof(R) * C) & (0 - sizeof(R) * C))) Chan {
     R v[C];
 };
 
@@ -909,10 +912,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 // grows the next chunk.  Each staged cell serves ~40 sample taps at paper
 // scale, so the L1 sees a few coalesced row loads per chunk instead of 8
 // scattered cells per sample.
-// LDS per wave: six 256-thread blocks per CU at C <= 4 (68 VGPRs), four at
-// C = 8 (108 VGPRs), the most that the registers allow in each case
+// LDS per wave: six 256-thread blocks per CU at C <= 4 (68 VGPRs), five at
+// C = 6 (97 VGPRs), four at C = 8 (108 VGPRs), the most that the registers
+// allow in each case (at C = 6, 6 KB and five blocks beat 9 KB and four by
+// 5-9 %)
 template <int C>
-constexpr int stage_bytes() { return C <= 4 ? 6144 : 9216; }
+constexpr int stage_bytes() { return C <= 6 ? 6144 : 9216; }
+template <int C>
+constexpr int march_waves_per_eu() { return C <= 4 ? 6 : (C <= 6 ? 5 : 4); }
 
 // a * b + c with a, b < 2^24 in one v_mad_u32_u24 (b wave-uniform; left to
 // itself the compiler spreads a two-term cell offset over more instructions)
@@ -945,9 +952,13 @@ __device__ __forceinline__ void lds_pair(const char* st, unsigned off, float (&a
             a[4 * h] = u.x; a[4 * h + 1] = u.y; a[4 * h + 2] = u.z; a[4 * h + 3] = u.w;
             b[4 * h] = v.x; b[4 * h + 1] = v.y; b[4 * h + 2] = v.z; b[4 * h + 3] = v.w;
         }
-    } else if constexpr (C == 2) {
-        const float2 u = *(const float2*)(st + off), v = *(const float2*)(st + off + 8);
-        a[0] = u.x; a[1] = u.y; b[0] = v.x; b[1] = v.y;
+    } else if constexpr (C % 2 == 0) {
+        // 8-byte aligned cells (C = 2, 6): pairs of channels
+#pragma unroll
+        for (int h = 0; h < C / 2; ++h) {
+            const float2 u = *(const float2*)(st + off + 8 * h), v = *(const float2*)(st + off + 4 * C + 8 * h);
+            a[2 * h] = u.x; a[2 * h + 1] = u.y; b[2 * h] = v.x; b[2 * h + 1] = v.y;
+        }
     } else {
         const float* q = (const float*)(st + off);
         a[0] = q[0];
@@ -962,9 +973,11 @@ __device__ __forceinline__ void stage_cell(const char* src, float* dst)
     if constexpr (C % 4 == 0) {
 #pragma unroll
         for (int h = 0; h < C / 4; ++h) ((float4*)dst)[h] = ((const float4*)src)[h];
-    } else if constexpr (C == 2) {
-        *(float2*)dst = *(const float2*)src;
+    } else if constexpr (C % 2 == 0) {
+#pragma unroll
+        for (int h = 0; h < C / 2; ++h) ((float2*)dst)[h] = ((const float2*)src)[h];
     } else {
+        static_assert(C == 1, "cells of 1, 2, 4, 6 or 8 channels");
         *dst = *(const float*)src;
     }
 }
@@ -974,7 +987,7 @@ __device__ __forceinline__ void stage_cell(const char* src, float* dst)
 // these, so a 5- or 6-channel image stored in 8-channel cells (K = 4, 5)
 // does not pay for the channels it does not use.
 template <int C, int KC = C>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4 ? 6 : 4))) k_march_lds(MarchArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<C>()))) k_march_lds(MarchArgs A)
 {
     static_assert(KC >= 1 && KC <= C, "used channels");
     constexpr int CB = 4 * C;                    // bytes per cell
@@ -1977,6 +1990,7 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
         case 1: PCR_WF(1, false); break;
         case 2: PCR_WF(2, false); break;
         case 4: PCR_WF(4, false); break;
+        case 6: PCR_WF(6, false); break;
         case 8: PCR_WF(8, false); break;
         default: return hipErrorInvalidValue;
         }
@@ -1984,6 +1998,7 @@ static hipError_t warp_fused_c(const pcr_grid& g, const PadLayout& L, int K, boo
         switch (L.C) {
         case 2: PCR_WF(2, true); break;
         case 4: PCR_WF(4, true); break;
+        case 6: PCR_WF(6, true); break;
         case 8: PCR_WF(8, true); break;
         default: return hipErrorInvalidValue;
         }
@@ -2060,6 +2075,7 @@ static hipError_t march_r(const PadLayout& L, int kc, const RayGeom& rg, const M
     case 1: PCR_MARCH(1); break;
     case 2: PCR_MARCH(2); break;
     case 4: PCR_MARCH(4); break;
+    case 6: PCR_MARCH(6); break;
     case 8: PCR_MARCH(8); break;
     default: return hipErrorInvalidValue;
     }
@@ -2119,18 +2135,15 @@ static hipError_t march_f32(const PadLayout& L, int kc, const RayGeom& rg, const
         case 1: k_march_lds<1><<<blocks, 256, 0, s>>>(A); break;
         case 2: k_march_f32<2, false><<<blocks, 256, 0, s>>>(A); break;
         case 4: k_march_lds<4><<<blocks, 256, 0, s>>>(A); break;
-        case 8:
-            // K = 4 and 5 use 5 and 6 of the 8 channels: the loads of the
-            // unused ones narrow to one or two dwords.  (Three of four, the
-            // 12-byte LDS reads of K = 2 in 4-channel cells or K = 6 in
-            // 8-channel ones, were slower than summing the zero channel:
-            // 183.6 against 145.6 us at K = 2.)
-            switch (kc) {
-            case 5: k_march_lds<8, 5><<<blocks, 256, 0, s>>>(A); break;
-            case 6: k_march_lds<8, 6><<<blocks, 256, 0, s>>>(A); break;
-            default: k_march_lds<8><<<blocks, 256, 0, s>>>(A); break;
-            }
+        case 6:
+            // K = 4 sums 5 of the 6 channels.  (Summing only the channels in
+            // use pays where the unused ones drop whole loads; 12-byte LDS
+            // reads, as for K = 2 in 4-channel cells, were slower than
+            // summing the zero channel: 183.6 against 145.6 us at K = 2.)
+            if (kc == 5) k_march_lds<6, 5><<<blocks, 256, 0, s>>>(A);
+            else k_march_lds<6><<<blocks, 256, 0, s>>>(A);
             break;
+        case 8: k_march_lds<8><<<blocks, 256, 0, s>>>(A); break;
         default: return hipErrorInvalidValue;
         }
     }

@@ -31,7 +31,7 @@ namespace pcr {
 struct PadLayout {
     int nx, ny, nz;
     int px, py, pz;      // padded dims in memory order (fast, mid, slow)
-    int C;               // channel stride (1, 2, 4 or 8)
+    int C;               // channel stride (1, 2, 4, 6 or 8)
     bool yfast;
     bool half = false;   // FP16 channels (FP32 compute only)
     float hs[8] = {1, 1, 1, 1, 1, 1, 1, 1};

@@ -158,10 +158,10 @@ def test_march_addressing_limit_is_rejected_before_any_launch():
     st = L.pcr_forward_project(C.byref(g), C.byref(G), _lib.PCR_F32, fake, fake, None)
     assert st == _lib.PCR_EINVAL
     assert b"addressing" in L.pcr_last_error()
-    # K = 4 fused image (8 FP32 channels, 32 B cells): 515 x 515 x 259 x 32 B = 2.2 GB
+    # K = 4 fused image (6 FP32 channels, 24 B cells): 515 x 515 x 343 x 24 B = 2.18 GB
     m = _lib.Model(4, _lib.PCR_F32, fake.value, fake.value, None)
     h = C.c_void_p()
-    g2 = _fake_grid((512, 512, 256))
+    g2 = _fake_grid((512, 512, 340))
     st = L.pcr_ctx_create(C.byref(g2), C.byref(m), _lib.PCR_F32, fake, _lib.PCR_F32, C.byref(h))
     assert st == _lib.PCR_EINVAL and not h.value
     assert b"addressing" in L.pcr_last_error()
