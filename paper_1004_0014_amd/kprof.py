@@ -30,7 +30,7 @@ def main():
     ap.add_argument("--config", default="paper",
                     help="paper, tiny, diff, precision, or serve-max: the largest volume and detector "
                          "of the serving configuration (512x512x160 over 480x480x320 mm, K = 5, "
-                         "1024x768 at 397/1024 mm), whose fused image (1.38 GB) exceeds the caches")
+                         "1024x768 at 397/1024 mm), whose fused image (1.04 GB) exceeds the caches")
     ap.add_argument("--angle", type=float, default=30.0)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--what", default="fused", choices=["fused", "adjoint", "backproject", "forward", "pca"])
