@@ -344,7 +344,7 @@ constexpr int yf_tile_x()
 }
 
 // y-fastest padded layout: a TX x 8 (x, y) tile per block, computed with
-// x-contiguous reads (4 TX-byte runs of each field), staged in LDS and
+// x-contiguous reads (runs of 4 TX bytes of each field), staged in LDS and
 // written as 8-cell runs along y.
 template <typename R, typename S, typename F, int C, bool TAN, bool H>
 __global__ void __launch_bounds__(256) k_warp_fused_yf(const F* __restrict__ f0,
@@ -912,10 +912,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 4
 // grows the next chunk.  Each staged cell serves ~40 sample taps at paper
 // scale, so the L1 sees a few coalesced row loads per chunk instead of 8
 // scattered cells per sample.
-// LDS per wave: six 256-thread blocks per CU at C <= 4 (68 VGPRs), five at
-// C = 6 (97 VGPRs), four at C = 8 (108 VGPRs), the most that the registers
-// allow in each case (at C = 6, 6 KB and five blocks beat 9 KB and four by
-// 5-9 %)
+// LDS per wave: six 256-thread blocks per CU at C <= 4 (74 VGPRs), five at
+// C = 6 (85-94 VGPRs), four at C = 8 (114 VGPRs), the most that the
+// registers allow in each case (at C = 6, 6 KB and five blocks beat 9 KB
+// and four by 5-9 % at paper scale)
 template <int C>
 constexpr int stage_bytes() { return C <= 6 ? 6144 : 9216; }
 template <int C>
