@@ -988,8 +988,8 @@ __device__ __forceinline__ void stage_cell(const char* src, float* dst)
 
 // KC: the channels whose sums are used (A.kc: the moments and the projection
 // read only those; the others stay zero); the sample loop accumulates only
-// these, so a 5- or 6-channel image stored in 8-channel cells (K = 4, 5)
-// does not pay for the channels it does not use.
+// these, so a 5-channel image stored in 6-channel cells (K = 4) does not pay
+// for the channel it does not use.
 template <int C, int KC = C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<C>()))) k_march_lds(MarchArgs A)
 {
