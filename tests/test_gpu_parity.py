@@ -102,8 +102,8 @@ def test_coarse_detector_and_long_steps(dtype):
         assert abs(np.vdot(pr, r) - np.vdot(f, bp)) <= tol * np.sum(np.abs(pr) * np.abs(r)), G.du
     if dtype == "f64":
         return
-    # the fused path (4- and 8-channel images) on the coarse detector
-    for K in (3, 5):
+    # the fused path (2-, 4- and 6-channel images) on the coarse detector
+    for K in (1, 3, 4, 5):
         mean, U = _smooth_model(g, K, seed=30 + K)
         mean_t, mean = rounded(mean, torch.float32)
         U_t, U = rounded(U, torch.float32)
@@ -116,7 +116,12 @@ def test_coarse_detector_and_long_steps(dtype):
         J, grad = ctx.cost_grad(y, G, 0.5 * w_true, 0.9, 0.01)
         Jo, go = oracle.cost_grad(g, G, f, mean, U, 0.5 * w_true, y_np, 0.9, 0.01)
         assert abs(J - Jo) <= 2e-5 * Jo, K
-        assert rel_l2(grad, go) <= 1e-4, K
+        # bounds as in test_cost_grad_channel_counts: a voxel within FP32
+        # rounding of a cell face may take the neighbouring cell's
+        # derivative; the two GPU gradient paths share the FP32 positions
+        assert rel_l2(grad, go) <= 5e-4, K
+        _, grad_adj = ctx.cost_grad(y, G, 0.5 * w_true, 0.9, 0.01, mode=L.GRAD_ADJOINT)
+        assert rel_l2(grad, grad_adj) <= 1e-5, K
         ctx.close()
 
 
